@@ -1,0 +1,239 @@
+"""Kinetic Monte-Carlo hysteresis loops, written out step by step in FP64 (Sec. II.1
+steps i-viii, Eqs. 1-5; loop protocol Sec. III.1; SAR conversion Sec. III.2.a).
+
+Readings of points the paper leaves open (applied identically by the GPU library):
+
+* Eq. 1 sums over the other particles j != i; the result mu0 H_dip is in tesla.
+* Field H_k = H_max cos(2 pi k / S) along x, constant during step k (steps of equal
+  length dt = 1/(f S)); a run is n_periods periods starting at +H_max; the first
+  n_discard periods are thrown away (Sec. III.1).
+* Working plane (step iii): u1 = easy axis n, u2 = the unit part of B_tot normal to
+  n. When that part vanishes (|B_perp| <= 1e-12 max(|B|, mu0 H_K)) u2 is the unit
+  part of the previous moment normal to n, else the normalised n x e, with e the
+  coordinate axis least aligned with n.
+* Initial moments m_i = sign(n_i . x) n_i with sign(0) = +1.
+* Eq. 5 is read as the probability to leave the current well c for the other well o:
+  P = nu_c/(nu_c+nu_o) (1 - exp(-(nu_c+nu_o) dt)), nu = nu0 exp(-(E3-E)/kT); it is
+  evaluated as sigma(a_o - a_c) * (-expm1(-nu0 dt (e^-a_c + e^-a_o))), which is the
+  same expression rearranged so that it cannot overflow. Jump iff u < P.
+  prob_form=1 selects the single-rate form 1 - exp(-nu_c dt) instead.
+* T = 0: steps vi-vii are skipped; K_eff = 0: the moment aligns with B_tot.
+* Area: A = M_S sum_k mu0H_k (m_x,k - m_x,k-1) over the kept steps (work done at
+  constant field per step), J/m^3; SAR = A f / rho.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import philox
+from . import sw
+
+MU0 = 4e-7 * np.pi
+KB = 1.380649e-23
+
+
+@dataclass
+class Params:
+    Ms: float = 4.0e5
+    Keff: float = 1.3e4
+    d: float = 12e-9
+    T: float = 300.0
+    tau0: float = 1e-10
+    rho: float = 5200.0
+    f: float = 1e5
+    mu0Hmax: float = 0.02
+    steps_per_period: int = 2000
+    n_periods: int = 3
+    n_discard: int = 2
+    dt_override: float = 0.0
+    prob_form: int = 0
+    interactions: int = 1
+
+    @classmethod
+    def from_dict(cls, d):
+        return cls(**{k: d[k] for k in cls.__dataclass_fields__ if k in d})
+
+
+def derived(p: Params):
+    """Sec. II.1 quantities: V, C = mu0 Ms V / 4pi, mu0 H_K = 2K/Ms, beta = K V / kT,
+    nu0 dt with dt = 1/(f S) (or dt_override)."""
+    V = np.pi * p.d ** 3 / 6.0
+    C = MU0 * p.Ms * V / (4.0 * np.pi)
+    BK = 2.0 * p.Keff / p.Ms if p.Keff > 0 else 0.0
+    beta = p.Keff * V / (KB * p.T) if p.T > 0 else np.inf
+    dt = p.dt_override if p.dt_override > 0 else 1.0 / (p.f * p.steps_per_period)
+    return dict(V=V, C=C, BK=BK, beta=beta, dt=dt, nu0dt=dt / p.tau0)
+
+
+def applied_field(k: int, p: Params) -> float:
+    """mu0 H_ext at step k (x component), Sec. II.1 and Sec. III.1."""
+    if p.dt_override > 0:
+        return p.mu0Hmax
+    return p.mu0Hmax * np.cos(2.0 * np.pi * k / p.steps_per_period)
+
+
+def dipolar_field(pos: np.ndarray, m: np.ndarray, C: float, chunk: int = 512) -> np.ndarray:
+    """Eq. 1: mu0 H_dip,i = C sum_{j != i} [3 (m_j . e_ij) e_ij - m_j] / r_ij^3, exact,
+    no cutoff. pos (N,3) in m, m (N,3) unit vectors; returns (N,3) in tesla."""
+    n = pos.shape[0]
+    out = np.zeros((n, 3))
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        r = pos[None, :, :] - pos[s:e, None, :]            # r_j - r_i
+        d2 = np.einsum("ijk,ijk->ij", r, r)
+        idx = np.arange(s, e)
+        d2[idx - s, idx] = np.inf                           # j == i excluded
+        inv = 1.0 / np.sqrt(d2)
+        eu = r * inv[:, :, None]
+        md = np.einsum("jk,ijk->ij", m, eu)
+        term = (3.0 * md[:, :, None] * eu - m[None, :, :]) * (inv ** 3)[:, :, None]
+        out[s:e] = term.sum(axis=1)
+    return C * out
+
+
+def working_plane(B: np.ndarray, n: np.ndarray, m: np.ndarray, BK: float):
+    """Step iii: in-plane frame (n, u2), reduced field (hx, hy) and theta0 of the
+    previous moment projected into the plane."""
+    bpar = np.einsum("ij,ij->i", B, n)
+    Bp = B - bpar[:, None] * n
+    bp = np.linalg.norm(Bp, axis=1)
+    Bn = np.linalg.norm(B, axis=1)
+    deg = bp <= 1e-12 * np.maximum(Bn, BK)
+    u2 = np.zeros_like(B)
+    ok = ~deg
+    u2[ok] = Bp[ok] / bp[ok, None]
+    if np.any(deg):
+        v = m - np.einsum("ij,ij->i", m, n)[:, None] * n
+        vn = np.linalg.norm(v, axis=1)
+        for i in np.nonzero(deg)[0]:
+            if vn[i] > 1e-12:
+                u2[i] = v[i] / vn[i]
+            else:
+                c = int(np.argmin(np.abs(n[i])))
+                e = np.zeros(3)
+                e[c] = 1.0
+                w = np.cross(n[i], e)
+                u2[i] = w / np.linalg.norm(w)
+    hx = bpar / BK
+    hy = np.where(deg, 0.0, bp / BK)
+    theta0 = np.arctan2(np.einsum("ij,ij->i", m, u2), np.einsum("ij,ij->i", m, n))
+    return u2, hx, hy, theta0
+
+
+def transition_probability(a_c, a_o, nu0dt, prob_form: int = 0):
+    """Eq. 5 (prob_form 0) or the single-rate form (prob_form 1); a = barrier / kT."""
+    if prob_form == 1:
+        return -np.expm1(-nu0dt * np.exp(-a_c))
+    with np.errstate(over="ignore"):
+        sig = 1.0 / (1.0 + np.exp(a_c - a_o))
+    return sig * (-np.expm1(-nu0dt * (np.exp(-a_c) + np.exp(-a_o))))
+
+
+@dataclass
+class StepInfo:
+    B: np.ndarray
+    hx: np.ndarray
+    hy: np.ndarray
+    theta0: np.ndarray
+    theta_c: np.ndarray
+    theta_o: np.ndarray
+    e_c: np.ndarray
+    e_o: np.ndarray
+    e3: np.ndarray
+    two: np.ndarray
+    P: np.ndarray
+    u: np.ndarray
+    jump: np.ndarray
+    u2: np.ndarray | None = None
+
+
+def step(pos, axes, m, k, p: Params, seed: int, stream: int, B_override=None):
+    """One synchronous step (steps ii-vii) for every particle from the start-of-step
+    moments ``m`` (Sec. II.2: fields are computed once per step). Returns (m_new, info)."""
+    dv = derived(p)
+    n = pos.shape[0]
+    Bx = applied_field(k, p)
+    if B_override is not None:
+        B = np.array(B_override, dtype=np.float64)
+    else:
+        B = np.zeros((n, 3))
+        if p.interactions and n > 1:
+            B += dipolar_field(pos, m, dv["C"])
+        B[:, 0] += Bx
+    if p.Keff <= 0:
+        Bn = np.linalg.norm(B, axis=1)
+        m_new = np.where(Bn[:, None] > 0, B / np.where(Bn > 0, Bn, 1.0)[:, None], m)
+        z = np.zeros(n)
+        return m_new, StepInfo(B, z, z, z, z, z, z, z, z, np.zeros(n, bool), z, z,
+                               np.zeros(n, bool))
+    u2, hx, hy, theta0 = working_plane(B, axes, m, dv["BK"])
+    theta, is_min, count = sw.stationary_points(hx, hy)
+    th_c, e_c, th_o, e_o, e3, two = sw.classify(theta0, theta, is_min, count, hx, hy)
+    th_new = th_c.copy()
+    P = np.zeros(n)
+    u = np.full(n, np.nan)
+    jump = np.zeros(n, dtype=bool)
+    if p.T > 0:
+        u = philox.uniforms(seed, stream, k, n)
+        a_c = dv["beta"] * (e3 - e_c)
+        a_o = dv["beta"] * (e3 - e_o)
+        P = np.where(two, transition_probability(np.where(two, a_c, 0.0),
+                                                 np.where(two, a_o, 0.0),
+                                                 dv["nu0dt"], p.prob_form), 0.0)
+        jump = two & (u < P)
+        th_new = np.where(jump, th_o, th_c)
+    m_new = np.cos(th_new)[:, None] * axes + np.sin(th_new)[:, None] * u2
+    info = StepInfo(B, hx, hy, theta0, th_c, th_o, e_c, e_o, e3, two, P, u, jump, u2)
+    return m_new, info
+
+
+def initial_moments(axes: np.ndarray) -> np.ndarray:
+    s = np.where(axes[:, 0] >= 0.0, 1.0, -1.0)
+    return axes * s[:, None]
+
+
+@dataclass
+class LoopResult:
+    H: np.ndarray                  # (S,) mu0 H_k, tesla
+    M: np.ndarray                  # (n_kept, S) M_S <m_x> after each step, A/m
+    area_per_np: np.ndarray        # (N,) J/m^3, mean over kept periods
+    area: float                    # J/m^3
+    sar: float                     # W/kg
+    m_final: np.ndarray
+    jumps: int = 0
+    trace: list = field(default_factory=list)
+
+
+def simulate(pos, axes, p: Params, seed: int, stream: int = 0, n_steps: int | None = None,
+             keep_trace: bool = False, m0=None) -> LoopResult:
+    """Whole run: n_periods x steps_per_period synchronous steps (Sec. III.1)."""
+    S = p.steps_per_period
+    total = p.n_periods * S if n_steps is None else n_steps
+    kept0 = p.n_discard * S
+    n_kept = max(0, p.n_periods - p.n_discard)
+    m = initial_moments(axes) if m0 is None else np.array(m0, dtype=np.float64)
+    n = pos.shape[0]
+    area = np.zeros(n)
+    Mrec = np.zeros((max(n_kept, 1), S))
+    Hrec = np.array([applied_field(k, p) for k in range(S)])
+    jumps = 0
+    trace = []
+    for k in range(total):
+        m_new, info = step(pos, axes, m, k, p, seed, stream)
+        jumps += int(info.jump.sum())
+        if k >= kept0:
+            area += p.Ms * applied_field(k, p) * (m_new[:, 0] - m[:, 0])
+            Mrec[(k - kept0) // S, k % S] = p.Ms * m_new[:, 0].mean()
+        if keep_trace:
+            trace.append(info)
+        m = m_new
+    area_np = area / max(n_kept, 1)
+    A = float(area_np.mean()) if n else 0.0
+    return LoopResult(Hrec, Mrec[:n_kept], area_np, A, A * p.f / p.rho, m, jumps, trace)
+
+
+def sar_from_area(area, f, rho=5200.0):
+    """Sec. III.2.a: SAR = A f / rho (W/kg) for an area A in J/m^3."""
+    return area * f / rho
