@@ -1,0 +1,164 @@
+/*
+ * mhkmc: kinetic Monte-Carlo hysteresis loops of interacting magnetic nanoparticles
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: R. P. Tan, J. Carrey and M. Respaud, "Magnetic hyperthermia properties of
+ * nanoparticles inside lysosomes using kinetic Monte-Carlo simulations", arXiv:1407.2737.
+ * Each time step of a sinusoidal applied field (Sec. II.1, steps i-viii):
+ *   - the exact dipolar field on every particle from all others (Eq. 1),
+ *   - the Stoner-Wohlfarth minima and lower maximum of Eq. 2 in the particle's
+ *     working plane, and the fall of the moment into its basin (steps iii-v),
+ *   - the two-state switching probability of Eqs. 3-5 and a uniform draw (vi-vii),
+ *   - accumulation of the loop and of its area; SAR = A f / rho (Sec. III.2.a).
+ * All particles move synchronously from the start-of-step state (Sec. II.2).
+ *
+ * Conventions
+ *   - SI units throughout: positions in m, M_S in A/m, K_eff in J/m^3, mu0 H in T,
+ *     areas in J/m^3, SAR in W/kg.
+ *   - Every function returns 0 on success or a negative MH_E* code; no exception or
+ *     abort crosses this boundary. mh_strerror() names a code.
+ *   - Input arrays are host memory, read during the call and copied; the caller keeps
+ *     ownership. Output arrays are host memory of the documented size, allocated by
+ *     the caller. The library owns all device memory it allocates until the matching
+ *     destroy call.
+ *   - One assembly must not be driven from two threads at once.
+ */
+#ifndef MHKMC_H
+#define MHKMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define MH_OK 0
+#define MH_EINVAL -1     /* invalid argument (null pointer, bad size, non-finite value) */
+#define MH_EOVERLAP -2   /* two particles closer than one diameter */
+#define MH_ENOMEM -3     /* device or host allocation failed */
+#define MH_EDEVICE -4    /* HIP runtime error (no device, launch failure) */
+#define MH_ENOTREADY -5  /* results requested before a run finished */
+#define MH_ENUMERIC -6   /* non-finite value produced during a run */
+#define MH_EBUDGET -7    /* request exceeds the configured device-memory budget */
+
+/* precision of the dipolar sum (the per-particle barrier step is always FP64) */
+#define MH_FP64 0        /* Eq. 1 summed in FP64 */
+#define MH_FP32_FIELD 1  /* Eq. 1 summed in FP32 from FP32 positions / d */
+#define MH_BF16X3_WM 2   /* fixed interaction matrix W (3N x 3N) times moments on MFMA,
+                            BF16 hi+lo split, FP32 accumulation */
+
+/* probability of leaving the current well during one step */
+#define MH_P_TWO_STATE 0   /* Eq. 5: nu_c/(nu_c+nu_o) (1 - exp(-(nu_c+nu_o) dt)) */
+#define MH_P_SINGLE_RATE 1 /* 1 - exp(-nu_c dt): the one-rate limit of Eq. 5 */
+
+typedef struct mh_ctx mh_ctx;
+typedef struct mh_asm mh_asm;
+
+/* Material, field and protocol of one assembly (Sec. II.1, Sec. II.2 defaults). */
+typedef struct {
+  double Ms;          /* saturation magnetisation, A/m (> 0) */
+  double Keff;        /* uniaxial anisotropy, J/m^3 (>= 0; 0 = moments follow the field) */
+  double d;           /* particle diameter, m (> 0); V = pi d^3 / 6 */
+  double T;           /* temperature, K (>= 0; 0 = no thermal jumps, step vii skipped) */
+  double tau0;        /* inverse attempt frequency 1/nu0, s (> 0; paper: 1e-10) */
+  double rho;         /* density for SAR, kg/m^3 (> 0; paper: 5200) */
+  double f;           /* field frequency, Hz (> 0) */
+  double mu0Hmax;     /* field amplitude, T (>= 0); field along +x, H_k = Hmax cos(2 pi k/S) */
+  double dt_override; /* > 0: constant field mu0Hmax along x and steps of this length, s */
+  int32_t steps_per_period; /* S, even, >= 2 (paper: 2000) */
+  int32_t n_periods;        /* periods run (>= 1) */
+  int32_t n_discard;        /* leading periods not kept (0 <= n_discard < n_periods) */
+  int32_t prob_form;        /* MH_P_TWO_STATE or MH_P_SINGLE_RATE */
+  int32_t precision;        /* MH_FP64, MH_FP32_FIELD or MH_BF16X3_WM */
+  int32_t interactions;     /* 1: Eq. 1 on; 0: off (the paper's validation mode, Sec. II.3) */
+  int32_t reserved[2];      /* must be 0 */
+} mh_params;
+
+/* Context bound to one HIP device; owns a default stream. */
+int mh_ctx_create(int device, mh_ctx** out);
+int mh_ctx_destroy(mh_ctx* ctx);
+
+/* Assembly of n particles (Sec. II.1).
+ *   pos   n x 3 row-major centres, m. Pairs closer than d (1 - 1e-9) are rejected
+ *         with MH_EOVERLAP.
+ *   axes  n_axes_sets x n x 3 easy axes (normalised on input, zero rows rejected).
+ *         Replica r uses axis set r mod n_axes_sets: one set shared by all replicas,
+ *         or one per replica (averaging over axis orientations, Sec. III.1).
+ * Initial moments are m_i = sign(n_i . x) n_i (sign(0) = +1). */
+int mh_create_assembly(mh_ctx* ctx, int64_t n, const double* pos, const double* axes,
+                       int64_t n_axes_sets, const mh_params* params, mh_asm** out);
+int mh_destroy_assembly(mh_asm* a);
+
+/* Runs n_periods x steps_per_period steps for n_replicas independent replicas.
+ * Replica r draws its uniforms from Philox-4x64-10 with key (seed, r) and counter
+ * (i/4, k, 0, 0), word i mod 4, u = (word >> 11) 2^-53; it jumps iff u < P.
+ * hip_stream: a hipStream_t, or NULL for the context's stream. Asynchronous with
+ * respect to the host; results are read after mh_sync. */
+int mh_run_loops(mh_asm* a, int64_t n_replicas, uint64_t seed, void* hip_stream);
+
+/* Runs several assemblies together (uneven sizes, different materials and fields):
+ * one fused launch per step covers every assembly that still has steps to run, and
+ * small assemblies run all their steps inside one launch. Each assembly's results are
+ * those it would give alone with the same (n_replicas, seed). */
+int mh_run_batch(mh_asm* const* asms, int32_t count, const int64_t* n_replicas,
+                 const uint64_t* seeds, void* hip_stream);
+
+/* Waits for the assembly's last run. */
+int mh_sync(mh_asm* a);
+
+/* Loop of one replica for kept period p (0 <= p < n_periods - n_discard):
+ *   H_T[k]   applied mu0 H_k (T), k = 0 .. S-1
+ *   M_Apm[k] M_S <m_x> after step k (A/m). */
+int mh_get_loop(mh_asm* a, int64_t replica, int32_t period, double* H_T, double* M_Apm);
+
+/* Loop area A (J/m^3: mean over particles and kept periods, averaged over replicas)
+ * with its standard error over replicas, SAR = A f / rho (W/kg) and its standard error.
+ * area_per_np: n replica-mean per-particle areas, or NULL. */
+int mh_get_sar(mh_asm* a, double* sar_Wkg, double* sar_se, double* area_Jm3, double* area_se,
+               double* area_per_np);
+
+/* Per-replica loop areas (n_replicas values, J/m^3). */
+int mh_get_replica_areas(mh_asm* a, double* area);
+
+/* Current moments of one replica (n x 3). */
+int mh_get_moments(mh_asm* a, int64_t replica, double* m);
+
+/* Diagnostics for kernel-level parity. Run steps [k0, k1) of replica set
+ * (n_replicas, seed) starting from moments m_in (n_replicas x n x 3, or NULL to keep
+ * the current state), without resetting the area accumulators. When diag is not NULL
+ * the last step writes, per replica and particle, 8 doubles: total field B (3, T),
+ * switching probability P, jump flag, two-minima flag, 0, 0. */
+int mh_debug_steps(mh_asm* a, int64_t n_replicas, uint64_t seed, int64_t k0, int64_t k1,
+                   const double* m_in, double* diag);
+
+/* Raw Philox-4x64-10 blocks for explicit counters (n_blocks x 4 words in, out). */
+int mh_debug_philox(mh_ctx* ctx, uint64_t seed, uint64_t stream, int64_t n_blocks,
+                    const uint64_t* ctr, uint64_t* out);
+
+/* Stoner-Wohlfarth fall for reduced fields (hx along the axis, hy >= 0 across it) and
+ * start angles theta0 in [-pi, pi]: writes n x 6 doubles (theta_c, e_c, theta_o, e_o, e3, two),
+ * energies in units of K V (Eq. 2 divided by K V), angles in (-pi, pi]. */
+int mh_debug_sw(mh_ctx* ctx, int64_t n, const double* hx, const double* hy,
+                const double* theta0, double* out);
+
+/* Dipolar field of Eq. 1 (T) for moments m (n x 3) of an assembly, as summed by the
+ * precision the assembly was created with. B_out: n x 3. */
+int mh_debug_field(mh_asm* a, const double* m, double* B_out);
+
+/* Launch timing (diagnostics for roofline reports). When on, every step-kernel launch
+ * is bracketed by a pair of HIP events on the stream it runs on. mh_ctx_get_timing
+ * waits for the recorded launches of one kind (0: tiled field+update step, 1: resident
+ * whole-run launch, 2: interaction-matrix step), returns their summed duration (ms) and
+ * count, and clears the record. */
+int mh_ctx_set_timing(mh_ctx* ctx, int on);
+int mh_ctx_get_timing(mh_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
+
+const char* mh_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHKMC_H */

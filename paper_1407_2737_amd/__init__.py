@@ -1,0 +1,245 @@
+"""Python binding of libmhkmc (include/mhkmc.h): argument marshalling only.
+
+Every step of the kinetic Monte-Carlo path runs in the library's HIP kernels; this
+module converts numpy arrays to pointers and return codes to exceptions. Importing it
+fails loudly when the built library is missing (build it with
+``python -m paper_1407_2737_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmhkmc.so")
+
+FP64, FP32_FIELD, BF16X3_WM = 0, 1, 2
+P_TWO_STATE, P_SINGLE_RATE = 0, 1
+ENOTREADY = -5
+
+SYMBOLS = [
+    "mh_ctx_create", "mh_ctx_destroy", "mh_create_assembly", "mh_destroy_assembly",
+    "mh_run_loops", "mh_run_batch", "mh_sync", "mh_get_loop", "mh_get_sar",
+    "mh_get_replica_areas", "mh_get_moments", "mh_debug_steps", "mh_debug_philox",
+    "mh_debug_sw", "mh_debug_field", "mh_strerror", "mh_ctx_set_timing", "mh_ctx_get_timing",
+]
+
+
+class MHError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {_lib().mh_strerror(code).decode()} ({code})")
+
+
+class Params(C.Structure):
+    _fields_ = [("Ms", C.c_double), ("Keff", C.c_double), ("d", C.c_double), ("T", C.c_double),
+                ("tau0", C.c_double), ("rho", C.c_double), ("f", C.c_double),
+                ("mu0Hmax", C.c_double), ("dt_override", C.c_double),
+                ("steps_per_period", C.c_int32), ("n_periods", C.c_int32),
+                ("n_discard", C.c_int32), ("prob_form", C.c_int32), ("precision", C.c_int32),
+                ("interactions", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+    @classmethod
+    def make(cls, precision: int = FP64, **kw) -> "Params":
+        p = cls()
+        defaults = dict(Ms=4.0e5, Keff=1.3e4, d=12e-9, T=300.0, tau0=1e-10, rho=5200.0, f=1e5,
+                        mu0Hmax=0.02, dt_override=0.0, steps_per_period=2000, n_periods=3,
+                        n_discard=2, prob_form=0, interactions=1)
+        defaults.update({k: v for k, v in kw.items() if k in defaults})
+        for k, v in defaults.items():
+            setattr(p, k, v)
+        p.precision = precision
+        return p
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1407_2737_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, u64, i32, dp = C.c_void_p, C.c_int64, C.c_uint64, C.c_int32, C.POINTER(C.c_double)
+        u64p = C.POINTER(C.c_uint64)
+        sig = {
+            "mh_ctx_create": ([C.c_int, C.POINTER(vp)], C.c_int),
+            "mh_ctx_destroy": ([vp], C.c_int),
+            "mh_create_assembly": ([vp, i64, dp, dp, i64, C.POINTER(Params), C.POINTER(vp)], C.c_int),
+            "mh_destroy_assembly": ([vp], C.c_int),
+            "mh_run_loops": ([vp, i64, u64, vp], C.c_int),
+            "mh_run_batch": ([C.POINTER(vp), i32, C.POINTER(i64), u64p, vp], C.c_int),
+            "mh_sync": ([vp], C.c_int),
+            "mh_get_loop": ([vp, i64, i32, dp, dp], C.c_int),
+            "mh_get_sar": ([vp, dp, dp, dp, dp, dp], C.c_int),
+            "mh_get_replica_areas": ([vp, dp], C.c_int),
+            "mh_get_moments": ([vp, i64, dp], C.c_int),
+            "mh_debug_steps": ([vp, i64, u64, i64, i64, dp, dp], C.c_int),
+            "mh_debug_philox": ([vp, u64, u64, i64, u64p, u64p], C.c_int),
+            "mh_debug_sw": ([vp, i64, dp, dp, dp, dp], C.c_int),
+            "mh_debug_field": ([vp, dp, dp], C.c_int),
+            "mh_strerror": ([C.c_int], C.c_char_p),
+            "mh_ctx_set_timing": ([vp, C.c_int], C.c_int),
+            "mh_ctx_get_timing": ([vp, i32, dp, C.POINTER(i64)], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _L = L
+    return _L
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise MHError(code, what)
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        a = a.reshape(shape)
+    return a
+
+
+class Context:
+    """A device context (mh_ctx_create)."""
+
+    def __init__(self, device: int = 0):
+        self._h = C.c_void_p()
+        _check(_lib().mh_ctx_create(device, C.byref(self._h)), "mh_ctx_create")
+
+    def close(self):
+        if self._h:
+            _lib().mh_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, on: bool):
+        _check(_lib().mh_ctx_set_timing(self._h, 1 if on else 0), "mh_ctx_set_timing")
+
+    def get_timing(self, kind: int = 0):
+        """(summed ms, launches) of the recorded step-kernel launches of one kind."""
+        ms = C.c_double()
+        cnt = C.c_int64()
+        _check(_lib().mh_ctx_get_timing(self._h, kind, C.byref(ms), C.byref(cnt)),
+               "mh_ctx_get_timing")
+        return ms.value, cnt.value
+
+    def debug_philox(self, seed: int, stream: int, ctr: np.ndarray) -> np.ndarray:
+        ctr = np.ascontiguousarray(ctr, dtype=np.uint64).reshape(-1, 4)
+        out = np.empty_like(ctr)
+        p = C.POINTER(C.c_uint64)
+        _check(_lib().mh_debug_philox(self._h, seed, stream, ctr.shape[0], ctr.ctypes.data_as(p),
+                                      out.ctypes.data_as(p)), "mh_debug_philox")
+        return out
+
+    def debug_sw(self, hx, hy, theta0) -> np.ndarray:
+        hx, hy, th = _f64(hx).ravel(), _f64(hy).ravel(), _f64(theta0).ravel()
+        out = np.empty((hx.shape[0], 6))
+        _check(_lib().mh_debug_sw(self._h, hx.shape[0], _dp(hx), _dp(hy), _dp(th), _dp(out)),
+               "mh_debug_sw")
+        return out
+
+
+class Assembly:
+    """An assembly of particles (mh_create_assembly) and its last run."""
+
+    def __init__(self, ctx: Context, pos, axes, params: Params, n_axes_sets: int = 1):
+        self.ctx = ctx
+        pos = _f64(pos)
+        self.n = pos.shape[0]
+        axes = _f64(axes, (n_axes_sets * self.n, 3))
+        self.params = params
+        self._h = C.c_void_p()
+        _check(_lib().mh_create_assembly(ctx._h, self.n, _dp(pos), _dp(axes), n_axes_sets,
+                                         C.byref(params), C.byref(self._h)), "mh_create_assembly")
+        self.R = 0
+
+    def close(self):
+        if self._h:
+            _lib().mh_destroy_assembly(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, n_replicas: int = 1, seed: int = 0, stream=None):
+        _check(_lib().mh_run_loops(self._h, n_replicas, seed, stream), "mh_run_loops")
+        self.R = n_replicas
+
+    def sync(self):
+        _check(_lib().mh_sync(self._h), "mh_sync")
+
+    def loop(self, replica: int = 0, period: int = 0):
+        S = self.params.steps_per_period
+        H = np.empty(S)
+        M = np.empty(S)
+        _check(_lib().mh_get_loop(self._h, replica, period, _dp(H), _dp(M)), "mh_get_loop")
+        return H, M
+
+    def sar(self, per_np: bool = False):
+        v = [C.c_double() for _ in range(4)]
+        apn = np.empty(self.n) if per_np else None
+        _check(_lib().mh_get_sar(self._h, *[C.byref(x) for x in v],
+                                 _dp(apn) if per_np else None), "mh_get_sar")
+        out = dict(sar=v[0].value, sar_se=v[1].value, area=v[2].value, area_se=v[3].value)
+        if per_np:
+            out["area_per_np"] = apn
+        return out
+
+    def replica_areas(self) -> np.ndarray:
+        out = np.empty(self.R)
+        _check(_lib().mh_get_replica_areas(self._h, _dp(out)), "mh_get_replica_areas")
+        return out
+
+    def moments(self, replica: int = 0) -> np.ndarray:
+        out = np.empty((self.n, 3))
+        _check(_lib().mh_get_moments(self._h, replica, _dp(out)), "mh_get_moments")
+        return out
+
+    def debug_steps(self, n_replicas: int, seed: int, k0: int, k1: int, m_in=None, diag=True):
+        m = None if m_in is None else _f64(m_in, (n_replicas * self.n, 3))
+        d = np.empty((n_replicas, self.n, 8)) if diag else None
+        _check(_lib().mh_debug_steps(self._h, n_replicas, seed, k0, k1,
+                                     _dp(m) if m is not None else None,
+                                     _dp(d) if d is not None else None), "mh_debug_steps")
+        self.R = n_replicas
+        return d
+
+    def debug_field(self, m) -> np.ndarray:
+        m = _f64(m, (self.n, 3))
+        out = np.empty((self.n, 3))
+        _check(_lib().mh_debug_field(self._h, _dp(m), _dp(out)), "mh_debug_field")
+        return out
+
+
+def run_batch(assemblies, n_replicas, seeds, stream=None):
+    """mh_run_batch over several assemblies in one fused launch sequence."""
+    k = len(assemblies)
+    hs = (C.c_void_p * k)(*[a._h.value for a in assemblies])
+    R = (C.c_int64 * k)(*n_replicas)
+    S = (C.c_uint64 * k)(*seeds)
+    _check(_lib().mh_run_batch(hs, k, R, S, stream), "mh_run_batch")
+    for a, r in zip(assemblies, n_replicas):
+        a.R = r
+
+
+def params_from_material(mat, precision: int = FP64) -> Params:
+    """Params from a workloads.Material."""
+    return Params.make(precision=precision, **mat.as_dict())

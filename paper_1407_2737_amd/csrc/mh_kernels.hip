@@ -1,0 +1,496 @@
+// Fused kMC step kernels for gfx950 (Tan, Carrey and Respaud, arXiv:1407.2737,
+// Sec. II.1 steps i-viii).
+//
+// Every step does, for every particle of every system (assembly x replica):
+//   ii   the exact dipolar field of Eq. 1 from the start-of-step moments,
+//   iii-v the working plane, Stoner-Wohlfarth extrema (Eq. 2) and the fall,
+//   vi-vii the two-state switching draw (Eqs. 3-5) from a Philox stream,
+// then writes the moment into the other half of a double buffer (all particles move
+// synchronously from the start-of-step state, Sec. II.2) and accumulates the
+// per-particle loop area and the loop record of the kept periods.
+//
+// Two launch forms of the same step:
+//   k_resident  one workgroup owns a whole small system and runs every step in one
+//               launch, positions and field-side moments resident in LDS;
+//   k_tiled     one launch per step over (system, i-tile, j-chunk) blocks; j-chunks
+//               are staged through LDS, partial fields are written to a buffer and
+//               the last block of an i-tile (device-scope counter) sums them in fixed
+//               order and runs the per-particle update.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mh_kernels.hpp"
+
+namespace mh {
+
+template <typename T>
+struct V4;
+template <>
+struct V4<double> {
+  using type = D4;
+};
+template <>
+struct V4<float> {
+  using type = F4;
+};
+
+template <typename T>
+__device__ __forceinline__ const typename V4<T>::type* pos_of(const SysDesc& s);
+template <>
+__device__ __forceinline__ const D4* pos_of<double>(const SysDesc& s) {
+  return s.pos64;
+}
+template <>
+__device__ __forceinline__ const F4* pos_of<float>(const SysDesc& s) {
+  return s.pos32;
+}
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type* mom_of(const SysDesc& s);
+template <>
+__device__ __forceinline__ D4* mom_of<double>(const SysDesc& s) {
+  return s.m64;
+}
+template <>
+__device__ __forceinline__ F4* mom_of<float>(const SysDesc& s) {
+  return s.m32;
+}
+
+// Eq. 1 term of source j on target i in reduced units (positions / d): accumulates
+// (3 (m.r) r / r^2 - m) / r^3 with r = p_j - p_i; a coincident pair (j == i)
+// contributes nothing.
+template <typename T, typename P4, typename M4>
+__device__ __forceinline__ void dip_pair(T xi, T yi, T zi, const P4& pj, const M4& mj, T& bx,
+                                         T& by, T& bz) {
+  const T dx = (T)pj.x - xi, dy = (T)pj.y - yi, dz = (T)pj.z - zi;
+  const T r2 = dx * dx + dy * dy + dz * dz;
+  T inv;
+  if constexpr (sizeof(T) == 4)
+    inv = r2 > (T)0 ? rsqrtf(r2) : (T)0;
+  else
+    inv = r2 > (T)0 ? (T)1 / sqrt(r2) : (T)0;
+  const T inv2 = inv * inv;
+  const T inv3 = inv2 * inv;
+  const T md = (T)mj.x * dx + (T)mj.y * dy + (T)mj.z * dz;
+  const T s = (T)3 * md * inv2;
+  bx += inv3 * (s * dx - (T)mj.x);
+  by += inv3 * (s * dy - (T)mj.y);
+  bz += inv3 * (s * dz - (T)mj.z);
+}
+
+// Steps iii-vii for particle i of system s with the reduced dipolar sum (ax, ay, az)
+// from the moments in buffer cur; writes buffer cur^1, accumulates the area, and
+// returns the new m_x.
+__device__ double np_epilogue(const SysDesc& s, int i, int64_t k, int cur, double ax, double ay,
+                              double az) {
+  if (s.field_only) {
+    double* d = s.diag + (int64_t)i * 8;
+    d[0] = s.Bscale * ax;
+    d[1] = s.Bscale * ay;
+    d[2] = s.Bscale * az;
+    return 0.0;
+  }
+  const double Bext = applied_field(s, k);
+  const double Bx = Bext + s.Bscale * ax, By = s.Bscale * ay, Bz = s.Bscale * az;
+  const D4 mo = s.m64[(int64_t)cur * s.stride + i];
+  const D4 nn = s.axes[i];
+  const NPResult r =
+      np_update(s.np, Bx, By, Bz, nn.x, nn.y, nn.z, mo.x, mo.y, mo.z, s.seed, s.stream, i, k);
+  const int nxt = cur ^ 1;
+  D4 mn;
+  mn.x = r.mx;
+  mn.y = r.my;
+  mn.z = r.mz;
+  mn.w = 0.0;
+  s.m64[(int64_t)nxt * s.stride + i] = mn;
+  F4 mf;
+  mf.x = (float)r.mx;
+  mf.y = (float)r.my;
+  mf.z = (float)r.mz;
+  mf.w = 0.f;
+  s.m32[(int64_t)nxt * s.stride + i] = mf;
+  if (k >= s.kept0) {
+    double sum = s.area[i], comp = s.area[s.n + i];
+    neumaier_add(sum, comp, s.Ms * Bext * (r.mx - mo.x));
+    s.area[i] = sum;
+    s.area[s.n + i] = comp;
+  }
+  if (s.diag) {
+    double* d = s.diag + (int64_t)i * 8;
+    d[0] = Bx;
+    d[1] = By;
+    d[2] = Bz;
+    d[3] = r.P;
+    d[4] = (double)r.jump;
+    d[5] = (double)r.two;
+    d[6] = 0.0;
+    d[7] = 0.0;
+  }
+  return r.mx;
+}
+
+// Fixed-order block sum of one double per thread (blockDim.x == 256).
+__device__ __forceinline__ double block_sum_256(double v, double* red) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Resident form: one workgroup of 256 threads per system, steps [k0, k1).
+// Dynamic LDS: pos[nmax] then mom[2][nmax] (field precision T).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ systems,
+                                                  int64_t k0, int64_t k1, int nmax) {
+  using P4 = typename V4<T>::type;
+  extern __shared__ __align__(32) unsigned char smem[];
+  P4* pos = reinterpret_cast<P4*>(smem);
+  P4* mom = pos + nmax;
+  __shared__ double red[4];
+  const SysDesc s = systems[blockIdx.x];
+  const int n = s.n;
+  const int tid = threadIdx.x;
+  const P4* gpos = pos_of<T>(s);
+  const P4* gmom = mom_of<T>(s);
+  const int cur0 = (int)(k0 & 1);
+  for (int j = tid; j < n; j += 256) {
+    pos[j] = gpos[j];
+    mom[(int64_t)cur0 * nmax + j] = gmom[(int64_t)cur0 * s.stride + j];
+  }
+  // threads per particle: largest power of two with P * n <= 256, at most 64
+  int P = 1;
+  while (P < 64 && 2 * P * n <= 256) P *= 2;
+  const int per_pass = 256 / P;
+  const int sub = tid % P;
+  const int64_t kend = k1 < (int64_t)s.total_steps ? k1 : (int64_t)s.total_steps;
+  __syncthreads();
+  for (int64_t k = k0; k < kend; ++k) {
+    const int cur = (int)(k & 1);
+    const P4* mc = mom + (int64_t)cur * nmax;
+    double mxsum = 0.0;
+    for (int base = 0; base < n; base += per_pass) {
+      const int i = base + tid / P;
+      T bx = 0, by = 0, bz = 0;
+      if (i < n) {
+        const P4 pi = pos[i];
+        for (int j = sub; j < n; j += P) dip_pair<T>((T)pi.x, (T)pi.y, (T)pi.z, pos[j], mc[j], bx, by, bz);
+      }
+      for (int off = P >> 1; off > 0; off >>= 1) {
+        bx += __shfl_xor(bx, off, 64);
+        by += __shfl_xor(by, off, 64);
+        bz += __shfl_xor(bz, off, 64);
+      }
+      if (i < n && sub == 0) {
+        const double mx = np_epilogue(s, i, k, cur, (double)bx, (double)by, (double)bz);
+        mxsum += mx;
+        if (s.field_only) continue;
+        const D4 m = s.m64[(int64_t)(cur ^ 1) * s.stride + i];
+        P4 v;
+        v.x = m.x;
+        v.y = m.y;
+        v.z = m.z;
+        v.w = 0;
+        mom[(int64_t)(cur ^ 1) * nmax + i] = v;
+      }
+    }
+    __syncthreads();
+    if (k >= s.kept0 && !s.field_only) {
+      const double tot = block_sum_256(mxsum, red);
+      if (tid == 0) s.recpart[k - s.kept0] = tot;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled form, one launch per step k. 256 targets per block (one per thread), a
+// chunk of JC sources staged through LDS.
+// ---------------------------------------------------------------------------
+template <typename T, int JC>
+__global__ __launch_bounds__(256) void k_tiled(const SysDesc* __restrict__ systems,
+                                               const Task* __restrict__ tasks,
+                                               typename V4<T>::type* __restrict__ part,
+                                               unsigned int* __restrict__ counters, int64_t k) {
+  using P4 = typename V4<T>::type;
+  __shared__ P4 spos[JC];
+  __shared__ P4 smom[JC];
+  __shared__ double red[4];
+  __shared__ int last;
+  const Task t = tasks[blockIdx.x];
+  const SysDesc& s = systems[t.sys];
+  if (k >= s.total_steps) return;
+  const int n = s.n;
+  const int tid = threadIdx.x;
+  const int cur = (int)(k & 1);
+  const P4* gpos = pos_of<T>(s);
+  const P4* gmom = mom_of<T>(s) + (int64_t)cur * s.stride;
+  const int j0 = t.chunk * JC;
+  const int jn = min(JC, n - j0);
+  for (int j = tid; j < JC; j += 256) {
+    P4 p, m;
+    if (j < jn) {
+      p = gpos[j0 + j];
+      m = gmom[j0 + j];
+    } else {  // padding: far away and without moment, contributes exactly zero
+      p.x = p.y = p.z = (T)1e15;
+      m.x = m.y = m.z = (T)0;
+      p.w = m.w = (T)0;
+    }
+    spos[j] = p;
+    smom[j] = m;
+  }
+  __syncthreads();
+  const int i = t.itile * 256 + tid;
+  T bx = 0, by = 0, bz = 0;
+  if (i < n) {
+    const P4 pi = gpos[i];
+    const T xi = (T)pi.x, yi = (T)pi.y, zi = (T)pi.z;
+#pragma unroll 8
+    for (int j = 0; j < JC; ++j) dip_pair<T>(xi, yi, zi, spos[j], smom[j], bx, by, bz);
+  }
+  P4 pr;
+  pr.x = bx;
+  pr.y = by;
+  pr.z = bz;
+  pr.w = 0;
+  part[t.part_off + (int64_t)t.chunk * 256 + tid] = pr;
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned prev = atomicAdd(&counters[t.tile_id], 1u);
+    last = (prev == (unsigned)(t.nchunks - 1));
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double ax = 0, ay = 0, az = 0;
+  for (int c = 0; c < t.nchunks; ++c) {
+    const P4 q = part[t.part_off + (int64_t)c * 256 + tid];
+    ax += (double)q.x;
+    ay += (double)q.y;
+    az += (double)q.z;
+  }
+  double mx = 0.0;
+  if (i < n) mx = np_epilogue(s, i, k, cur, ax, ay, az);
+  if (k >= s.kept0 && !s.field_only) {
+    const double tot = block_sum_256(mx, red);
+    if (tid == 0) s.recpart[(k - s.kept0) * s.ntiles + t.itile] = tot;
+  }
+  if (tid == 0) counters[t.tile_id] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// End of run: per-system loop record and area, per-assembly replica statistics.
+// ---------------------------------------------------------------------------
+// out_sys[sys] = loop area (J/m^3, mean over particles and kept periods);
+// rec_out rows: sum over tiles of the partial m_x sums (fixed order).
+__global__ __launch_bounds__(256) void k_finalize_sys(const SysDesc* __restrict__ systems) {
+  __shared__ double red[4];
+  const SysDesc s = systems[blockIdx.x];
+  const int tid = threadIdx.x;
+  double a = 0.0;
+  for (int i = tid; i < s.n; i += 256) a += s.area[i] + s.area[s.n + i];
+  const double tot = block_sum_256(a, red);
+  const int nk = (s.total_steps - s.kept0) / s.S;
+  if (tid == 0) s.sys_area[0] = nk > 0 ? tot / ((double)s.n * nk) : 0.0;
+  double* ro = s.rec;
+  const int rows = s.total_steps - s.kept0;
+  for (int r = tid; r < rows; r += 256) {
+    double v = 0.0;
+    for (int q = 0; q < s.ntiles; ++q) v += s.recpart[(int64_t)r * s.ntiles + q];
+    ro[r] = v;
+  }
+}
+
+// Replica statistics of one assembly: mean and standard error of the per-replica
+// areas (ddof = 1), single block.
+__global__ __launch_bounds__(256) void k_finalize_asm(const double* __restrict__ sys_area, int R,
+                                                      double* __restrict__ out) {
+  __shared__ double red[4];
+  double a = 0.0;
+  for (int r = threadIdx.x; r < R; r += 256) a += sys_area[r];
+  const double mean = block_sum_256(a, red) / R;
+  double v = 0.0;
+  for (int r = threadIdx.x; r < R; r += 256) {
+    const double d = sys_area[r] - mean;
+    v += d * d;
+  }
+  const double ss = block_sum_256(v, red);
+  if (threadIdx.x == 0) {
+    out[0] = mean;
+    out[1] = R > 1 ? sqrt(ss / (R - 1) / R) : 0.0;
+  }
+}
+
+// Replica-mean area of each particle (sum + compensation) / kept periods.
+__global__ void k_area_per_np(const double* __restrict__ area, int n, int R, int n_kept,
+                              double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0;
+  for (int r = 0; r < R; ++r) a += area[(int64_t)r * 2 * n + i] + area[(int64_t)r * 2 * n + n + i];
+  out[i] = n_kept > 0 ? a / ((double)R * n_kept) : 0.0;
+}
+
+// Start of a run: m_i = sign(n_i . x) n_i in buffer 0 (both precisions), zero the
+// area accumulators and the loop-record partials.
+__global__ void k_init(const SysDesc* __restrict__ systems) {
+  const SysDesc s = systems[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < s.n) {
+    const D4 a = s.axes[i];
+    const double sg = a.x >= 0.0 ? 1.0 : -1.0;
+    D4 m;
+    m.x = sg * a.x;
+    m.y = sg * a.y;
+    m.z = sg * a.z;
+    m.w = 0.0;
+    s.m64[i] = m;
+    F4 f;
+    f.x = (float)m.x;
+    f.y = (float)m.y;
+    f.z = (float)m.z;
+    f.w = 0.f;
+    s.m32[i] = f;
+    s.area[i] = 0.0;
+    s.area[s.n + i] = 0.0;
+  }
+  const int64_t rows = (int64_t)(s.total_steps - s.kept0) * s.ntiles;
+  for (int64_t r = i; r < rows; r += (int64_t)gridDim.x * blockDim.x) s.recpart[r] = 0.0;
+}
+
+// Copy FP64 moments of buffer b into the FP32 field copy.
+__global__ void k_sync32(const SysDesc* __restrict__ systems, int b) {
+  const SysDesc s = systems[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= s.n) return;
+  const D4 m = s.m64[(int64_t)b * s.stride + i];
+  F4 f;
+  f.x = (float)m.x;
+  f.y = (float)m.y;
+  f.z = (float)m.z;
+  f.w = 0.f;
+  s.m32[(int64_t)b * s.stride + i] = f;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics for unit parity
+// ---------------------------------------------------------------------------
+__global__ void k_philox_raw(uint64_t seed, uint64_t stream, const uint64_t* __restrict__ ctr,
+                             uint64_t* __restrict__ out, int64_t nblk) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblk) return;
+  uint64_t c0 = ctr[4 * b], c1 = ctr[4 * b + 1], c2 = ctr[4 * b + 2], c3 = ctr[4 * b + 3];
+  philox4x64_10(c0, c1, c2, c3, seed, stream);
+  out[4 * b] = c0;
+  out[4 * b + 1] = c1;
+  out[4 * b + 2] = c2;
+  out[4 * b + 3] = c3;
+}
+
+__global__ void k_sw(const double* __restrict__ hx, const double* __restrict__ hy,
+                     const double* __restrict__ th0, double* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const SWState r = sw_fall(hx[i], hy[i], th0[i]);
+  double* o = out + 6 * i;
+  o[0] = r.th_c;
+  o[1] = r.e_c;
+  o[2] = r.th_o;
+  o[3] = r.e_o;
+  o[4] = r.e3;
+  o[5] = r.two ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_resident(bool fp64, const SysDesc* d_sys, int nsys, int64_t k0, int64_t k1,
+                           int nmax, hipStream_t st) {
+  if (nsys == 0) return hipSuccess;
+  if (fp64) {
+    const size_t lds = (size_t)nmax * 3 * sizeof(D4);
+    hipLaunchKernelGGL(k_resident<double>, dim3(nsys), dim3(256), lds, st, d_sys, k0, k1, nmax);
+  } else {
+    const size_t lds = (size_t)nmax * 3 * sizeof(F4);
+    hipLaunchKernelGGL(k_resident<float>, dim3(nsys), dim3(256), lds, st, d_sys, k0, k1, nmax);
+  }
+  return hipGetLastError();
+}
+
+size_t resident_lds_bytes(bool fp64, int nmax) {
+  return fp64 ? (size_t)nmax * 3 * sizeof(D4) : (size_t)nmax * 3 * sizeof(F4);
+}
+
+hipError_t set_resident_lds_limit() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_resident<double>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_resident<float>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+}
+
+constexpr int kJC = 256;
+int tiled_chunk() { return kJC; }
+
+hipError_t launch_tiled(bool fp64, const SysDesc* d_sys, const Task* d_tasks, int ntasks,
+                        void* d_part, unsigned* d_ctr, int64_t k, hipStream_t st) {
+  if (ntasks == 0) return hipSuccess;
+  if (fp64)
+    hipLaunchKernelGGL((k_tiled<double, kJC>), dim3(ntasks), dim3(256), 0, st, d_sys, d_tasks,
+                       (D4*)d_part, d_ctr, k);
+  else
+    hipLaunchKernelGGL((k_tiled<float, kJC>), dim3(ntasks), dim3(256), 0, st, d_sys, d_tasks,
+                       (F4*)d_part, d_ctr, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st) {
+  if (nsys == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize_sys, dim3(nsys), dim3(256), 0, st, d_sys);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st) {
+  if (nsys == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init, dim3((nmax + 255) / 256, nsys), dim3(256), 0, st, d_sys);
+  return hipGetLastError();
+}
+
+hipError_t launch_sync32(const SysDesc* d_sys, int nsys, int nmax, int b, hipStream_t st) {
+  if (nsys == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sync32, dim3((nmax + 255) / 256, nsys), dim3(256), 0, st, d_sys, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_asm(const double* d_sys_area, int R, double* d_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_asm, dim3(1), dim3(256), 0, st, d_sys_area, R, d_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_area_per_np(const double* d_area, int n, int R, int n_kept, double* d_out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_area_per_np, dim3((n + 255) / 256), dim3(256), 0, st, d_area, n, R, n_kept,
+                     d_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_raw(uint64_t seed, uint64_t stream, const uint64_t* d_ctr, uint64_t* d_out,
+                             int64_t nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_philox_raw, dim3((unsigned)((nblk + 255) / 256)), dim3(256), 0, st, seed,
+                     stream, d_ctr, d_out, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_sw(const double* hx, const double* hy, const double* th0, double* out, int64_t n,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_sw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hx, hy, th0, out,
+                     n);
+  return hipGetLastError();
+}
+
+}  // namespace mh

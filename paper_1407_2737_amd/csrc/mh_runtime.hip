@@ -1,0 +1,841 @@
+// C-ABI runtime of mhkmc: validation, device memory, run orchestration and result
+// retrieval. The arithmetic of the method runs in the kernels of mh_kernels.hip
+// (and mh_wm.hip for the interaction-matrix form); this file only moves data and
+// launches work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/mhkmc.h"
+#include "mh_kernels.hpp"
+
+namespace mh {
+hipError_t launch_resident(bool fp64, const SysDesc* d_sys, int nsys, int64_t k0, int64_t k1,
+                           int nmax, hipStream_t st);
+size_t resident_lds_bytes(bool fp64, int nmax);
+hipError_t set_resident_lds_limit();
+int tiled_chunk();
+hipError_t launch_tiled(bool fp64, const SysDesc* d_sys, const Task* d_tasks, int ntasks,
+                        void* d_part, unsigned* d_ctr, int64_t k, hipStream_t st);
+hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st);
+hipError_t launch_init(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st);
+hipError_t launch_sync32(const SysDesc* d_sys, int nsys, int nmax, int b, hipStream_t st);
+hipError_t launch_finalize_asm(const double* d_sys_area, int R, double* d_out, hipStream_t st);
+hipError_t launch_area_per_np(const double* d_area, int n, int R, int n_kept, double* d_out,
+                              hipStream_t st);
+hipError_t launch_philox_raw(uint64_t seed, uint64_t stream, const uint64_t* d_ctr, uint64_t* d_out,
+                             int64_t nblk, hipStream_t st);
+hipError_t launch_sw(const double* hx, const double* hy, const double* th0, double* out, int64_t n,
+                     hipStream_t st);
+}  // namespace mh
+
+using namespace mh;
+
+namespace {
+
+constexpr double kMu0 = 4e-7 * 3.14159265358979323846;
+constexpr double kKB = 1.380649e-23;
+
+// Device buffer that grows on demand.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int ensure(size_t bytes) {
+    if (bytes <= cap) return MH_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipMalloc(&p, bytes) != hipSuccess) return MH_ENOMEM;
+    cap = bytes;
+    return MH_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+struct PinBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  int ensure(size_t bytes) {
+    if (bytes <= cap) return MH_OK;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return MH_ENOMEM;
+    cap = bytes;
+    return MH_OK;
+  }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+}  // namespace
+
+struct mh_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 256;
+  DevBuf d_sys, d_tasks, d_part, d_ctr;
+  PinBuf h_stage;
+  // optional per-launch timing of the step kernels (event pairs around each launch)
+  int timing = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_kind;  // 0: tiled step, 1: resident run, 2: matrix step
+};
+
+struct mh_asm {
+  mh_ctx* ctx = nullptr;
+  int64_t n = 0;
+  int64_t n_axes_sets = 1;
+  mh_params p{};
+  // geometry
+  DevBuf pos64, pos32, axes;
+  // run state
+  int64_t R = 0;
+  uint64_t seed = 0;
+  bool ran = false;
+  int ntiles = 1;
+  int resident = 0;
+  DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp;
+  int state_parity = 0;  // the current moments live in buffer state_parity
+  hipEvent_t done = nullptr;
+  // host copy of the per-run system descriptors (for diagnostics re-runs)
+};
+
+namespace {
+
+inline int set_dev(mh_ctx* c) {
+  return hipSetDevice(c->device) == hipSuccess ? MH_OK : MH_EDEVICE;
+}
+
+int total_steps(const mh_params& p) { return p.n_periods * p.steps_per_period; }
+int kept0(const mh_params& p) { return p.n_discard * p.steps_per_period; }
+int n_kept(const mh_params& p) { return p.n_periods - p.n_discard; }
+
+int validate_params(const mh_params* p) {
+  if (!p) return MH_EINVAL;
+  const double v[] = {p->Ms, p->Keff, p->d, p->T, p->tau0, p->rho, p->f, p->mu0Hmax,
+                      p->dt_override};
+  for (double x : v)
+    if (!std::isfinite(x)) return MH_EINVAL;
+  if (p->Ms <= 0 || p->Keff < 0 || p->d <= 0 || p->T < 0 || p->tau0 <= 0 || p->rho <= 0 ||
+      p->f <= 0 || p->mu0Hmax < 0 || p->dt_override < 0)
+    return MH_EINVAL;
+  if (p->steps_per_period < 2 || (p->steps_per_period & 1)) return MH_EINVAL;
+  if (p->n_periods < 1 || p->n_discard < 0 || p->n_discard >= p->n_periods) return MH_EINVAL;
+  if ((int64_t)p->n_periods * p->steps_per_period > (int64_t)1 << 30) return MH_EINVAL;
+  if (p->prob_form != MH_P_TWO_STATE && p->prob_form != MH_P_SINGLE_RATE) return MH_EINVAL;
+  if (p->precision != MH_FP64 && p->precision != MH_FP32_FIELD && p->precision != MH_BF16X3_WM)
+    return MH_EINVAL;
+  if (p->interactions != 0 && p->interactions != 1) return MH_EINVAL;
+  if (p->reserved[0] || p->reserved[1]) return MH_EINVAL;
+  return MH_OK;
+}
+
+// Pairs closer than d (1 - 1e-9): cell list with cell size d.
+int check_overlap(int64_t n, const double* pos, double d) {
+  const double lim = d * (1.0 - 1e-9);
+  const double lim2 = lim * lim;
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  for (int64_t i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c) lo[c] = std::min(lo[c], pos[3 * i + c]);
+  std::unordered_map<int64_t, std::vector<int64_t>> cells;
+  cells.reserve((size_t)n * 2);
+  auto key = [](int64_t a, int64_t b, int64_t c) {
+    return (a & 0x1FFFFF) | ((b & 0x1FFFFF) << 21) | ((c & 0x1FFFFF) << 42);
+  };
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t cx = (int64_t)std::floor((pos[3 * i] - lo[0]) / d);
+    const int64_t cy = (int64_t)std::floor((pos[3 * i + 1] - lo[1]) / d);
+    const int64_t cz = (int64_t)std::floor((pos[3 * i + 2] - lo[2]) / d);
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          auto it = cells.find(key(cx + dx, cy + dy, cz + dz));
+          if (it == cells.end()) continue;
+          for (int64_t j : it->second) {
+            const double ex = pos[3 * j] - pos[3 * i], ey = pos[3 * j + 1] - pos[3 * i + 1],
+                         ez = pos[3 * j + 2] - pos[3 * i + 2];
+            if (ex * ex + ey * ey + ez * ez < lim2) return MH_EOVERLAP;
+          }
+        }
+    cells[key(cx, cy, cz)].push_back(i);
+  }
+  return MH_OK;
+}
+
+bool wants_resident(const mh_asm* a, int64_t nsys_total) {
+  if (a->p.precision == MH_BF16X3_WM) return false;
+  const bool fp64 = a->p.precision == MH_FP64;
+  const int64_t cap = fp64 ? 1024 : 2048;
+  if (a->n > cap) return false;
+  if (a->n <= 256) return true;
+  // a single workgroup per system pays off once many systems fill the device
+  return nsys_total >= 4 * a->ctx->n_cu && a->n <= (fp64 ? 512 : 1024);
+}
+
+// (Re)allocate a replica set and its per-run buffers.
+int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident) {
+  const int64_t n = a->n;
+  const int JC = tiled_chunk();
+  a->resident = resident ? 1 : 0;
+  a->ntiles = resident ? 1 : (int)((n + 255) / 256);
+  (void)JC;
+  const int64_t rows = (int64_t)n_kept(a->p) * a->p.steps_per_period;
+  int e;
+  if ((e = a->m64.ensure(sizeof(D4) * 2 * R * n))) return e;
+  if ((e = a->m32.ensure(sizeof(F4) * 2 * R * n))) return e;
+  if ((e = a->area.ensure(sizeof(double) * 2 * R * n))) return e;
+  if ((e = a->recpart.ensure(sizeof(double) * R * rows * a->ntiles + 8))) return e;
+  if ((e = a->rec.ensure(sizeof(double) * R * rows + 8))) return e;
+  if ((e = a->sys_area.ensure(sizeof(double) * R))) return e;
+  if ((e = a->stats.ensure(sizeof(double) * 4))) return e;
+  a->R = R;
+  a->seed = seed;
+  return MH_OK;
+}
+
+SysDesc make_desc(const mh_asm* a, int64_t r) {
+  const mh_params& p = a->p;
+  SysDesc s{};
+  const int64_t n = a->n;
+  s.pos64 = a->pos64.as<D4>();
+  s.pos32 = a->pos32.as<F4>();
+  s.axes = a->axes.as<D4>() + (r % a->n_axes_sets) * n;
+  s.m64 = a->m64.as<D4>() + r * n;
+  s.m32 = a->m32.as<F4>() + r * n;
+  s.area = a->area.as<double>() + r * 2 * n;
+  const int64_t rows = (int64_t)n_kept(p) * p.steps_per_period;
+  s.recpart = a->recpart.as<double>() + r * rows * a->ntiles;
+  s.rec = a->rec.as<double>() + r * rows;
+  s.sys_area = a->sys_area.as<double>() + r;
+  s.diag = nullptr;
+  s.stride = a->R * n;
+  s.seed = a->seed;
+  s.stream = (uint64_t)r;
+  const double V = 3.14159265358979323846 * p.d * p.d * p.d / 6.0;
+  s.np.BK = p.Keff > 0 ? 2.0 * p.Keff / p.Ms : 0.0;
+  s.np.BK_inv = p.Keff > 0 ? p.Ms / (2.0 * p.Keff) : 0.0;
+  s.np.beta = p.T > 0 ? p.Keff * V / (kKB * p.T) : 0.0;
+  const double dt = p.dt_override > 0 ? p.dt_override : 1.0 / (p.f * p.steps_per_period);
+  s.np.nu0dt = dt / p.tau0;
+  s.np.prob_form = p.prob_form;
+  s.np.thermal = p.T > 0 ? 1 : 0;
+  s.np.aniso = p.Keff > 0 ? 1 : 0;
+  s.Bmax = p.mu0Hmax;
+  s.Bscale = p.interactions ? kMu0 * p.Ms / 24.0 : 0.0;
+  s.Ms = p.Ms;
+  s.n = (int32_t)n;
+  s.ntiles = a->ntiles;
+  s.S = p.steps_per_period;
+  s.total_steps = total_steps(p);
+  s.kept0 = kept0(p);
+  s.static_field = p.dt_override > 0 ? 1 : 0;
+  s.field_only = 0;
+  return s;
+}
+
+struct Plan {
+  std::vector<SysDesc> res64, res32, til64, til32;
+  std::vector<Task> tasks64, tasks32;
+  int nmax_res64 = 0, nmax_res32 = 0;
+  int64_t part64 = 0, part32 = 0;  // partial-sum entries
+  int nctr = 0;
+  int64_t kmax = 0;
+  int nmax_all = 0;
+};
+
+void add_tiled(Plan& pl, std::vector<SysDesc>& sys, std::vector<Task>& tasks, int64_t& part,
+               const SysDesc& s) {
+  const int JC = tiled_chunk();
+  const int sidx = (int)sys.size();
+  sys.push_back(s);
+  const int nch = (s.n + JC - 1) / JC;
+  for (int it = 0; it < s.ntiles; ++it) {
+    const int64_t off = part;
+    part += (int64_t)nch * 256;
+    const int tid = pl.nctr++;
+    for (int c = 0; c < nch; ++c) {
+      Task t{};
+      t.sys = sidx;
+      t.itile = it;
+      t.chunk = c;
+      t.nchunks = nch;
+      t.part_off = off;
+      t.tile_id = tid;
+      tasks.push_back(t);
+    }
+  }
+}
+
+// Descriptor array for a group, uploaded through the pinned stage into the device
+// scratch at byte offset `off`. Returns the device pointer.
+template <typename T>
+T* stage_upload(mh_ctx* c, const std::vector<T>& v, size_t& off, hipStream_t st) {
+  if (v.empty()) return nullptr;
+  const size_t bytes = sizeof(T) * v.size();
+  off = (off + 255) & ~(size_t)255;
+  std::memcpy(static_cast<char*>(c->h_stage.p) + off, v.data(), bytes);
+  T* d = reinterpret_cast<T*>(c->d_sys.as<char>() + off);
+  (void)hipMemcpyAsync(d, static_cast<char*>(c->h_stage.p) + off, bytes, hipMemcpyHostToDevice, st);
+  off += bytes;
+  return d;
+}
+
+// Event pair around a launch when timing is on; returns the index of the pair or -1.
+int timing_begin(mh_ctx* c, hipStream_t st, int kind) {
+  if (!c->timing) return -1;
+  if (c->ev_used + 2 > c->ev_pool.size()) {
+    for (int q = 0; q < 512; ++q) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      c->ev_pool.push_back(e);
+    }
+  }
+  const int idx = (int)c->ev_used;
+  c->ev_used += 2;
+  c->ev_kind.push_back(kind);
+  (void)hipEventRecord(c->ev_pool[idx], st);
+  return idx;
+}
+void timing_end(mh_ctx* c, hipStream_t st, int idx) {
+  if (idx >= 0) (void)hipEventRecord(c->ev_pool[idx + 1], st);
+}
+
+struct RunOpts {
+  bool init = true;          // fresh run: initial moments, zero accumulators
+  int64_t k0 = 0, k1 = -1;   // step range (-1: to the end)
+  bool finalize = true;
+  bool field_only = false;
+  double* diag = nullptr;    // device diag buffer base (per asm: R*n*8)
+};
+
+int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
+                const std::vector<uint64_t>& seeds, hipStream_t st, const RunOpts& o) {
+  if (asms.empty()) return MH_OK;
+  mh_ctx* c = asms[0]->ctx;
+  for (auto* a : asms)
+    if (a->ctx != c) return MH_EINVAL;
+  if (set_dev(c)) return MH_EDEVICE;
+  if (!st) st = c->stream;
+  int64_t nsys_total = 0;
+  for (size_t q = 0; q < asms.size(); ++q) nsys_total += Rs[q];
+  Plan pl;
+  std::vector<std::pair<mh_asm*, std::pair<int, int>>> fin;  // asm -> range in all-sys list
+  std::vector<SysDesc> all;
+  for (size_t q = 0; q < asms.size(); ++q) {
+    mh_asm* a = asms[q];
+    if (a->p.precision == MH_BF16X3_WM) return MH_EINVAL;  // handled by the matrix path
+    const bool res = wants_resident(a, nsys_total);
+    if (o.init) {
+      int e = prepare_run(a, Rs[q], seeds[q], res);
+      if (e) return e;
+    }
+    const bool fp64 = a->p.precision == MH_FP64;
+    const int first = (int)all.size();
+    for (int64_t r = 0; r < a->R; ++r) {
+      SysDesc s = make_desc(a, r);
+      s.field_only = o.field_only ? 1 : 0;
+      if (o.diag) s.diag = o.diag + r * a->n * 8;
+      all.push_back(s);
+      if (a->resident) {
+        (fp64 ? pl.res64 : pl.res32).push_back(s);
+        int& nm = fp64 ? pl.nmax_res64 : pl.nmax_res32;
+        nm = std::max(nm, (int)a->n);
+      } else if (fp64) {
+        add_tiled(pl, pl.til64, pl.tasks64, pl.part64, s);
+      } else {
+        add_tiled(pl, pl.til32, pl.tasks32, pl.part32, s);
+      }
+      pl.kmax = std::max<int64_t>(pl.kmax, s.total_steps);
+      pl.nmax_all = std::max(pl.nmax_all, (int)a->n);
+    }
+    fin.push_back({a, {first, (int)all.size()}});
+  }
+  // upload descriptors and tasks
+  size_t bytes = 0;
+  auto add = [&](size_t b) { bytes = ((bytes + 255) & ~(size_t)255) + b; };
+  add(sizeof(SysDesc) * all.size());
+  add(sizeof(SysDesc) * pl.res64.size());
+  add(sizeof(SysDesc) * pl.res32.size());
+  add(sizeof(SysDesc) * pl.til64.size());
+  add(sizeof(SysDesc) * pl.til32.size());
+  add(sizeof(Task) * pl.tasks64.size());
+  add(sizeof(Task) * pl.tasks32.size());
+  bytes += 256;
+  if (hipStreamSynchronize(st) != hipSuccess) return MH_EDEVICE;  // stage reuse
+  int e;
+  if ((e = c->h_stage.ensure(bytes))) return e;
+  if ((e = c->d_sys.ensure(bytes))) return e;
+  size_t off = 0;
+  SysDesc* d_all = stage_upload(c, all, off, st);
+  SysDesc* d_res64 = stage_upload(c, pl.res64, off, st);
+  SysDesc* d_res32 = stage_upload(c, pl.res32, off, st);
+  SysDesc* d_til64 = stage_upload(c, pl.til64, off, st);
+  SysDesc* d_til32 = stage_upload(c, pl.til32, off, st);
+  Task* d_t64 = stage_upload(c, pl.tasks64, off, st);
+  Task* d_t32 = stage_upload(c, pl.tasks32, off, st);
+  if ((e = c->d_part.ensure(sizeof(D4) * (pl.part64 + 1) + sizeof(F4) * (pl.part32 + 1)))) return e;
+  if ((e = c->d_ctr.ensure(sizeof(unsigned) * (pl.nctr + 1)))) return e;
+  D4* part64 = c->d_part.as<D4>();
+  F4* part32 = reinterpret_cast<F4*>(part64 + pl.part64 + 1);
+  if (hipMemsetAsync(c->d_ctr.p, 0, sizeof(unsigned) * (pl.nctr + 1), st) != hipSuccess)
+    return MH_EDEVICE;
+  if (o.init) {
+    if (launch_init(d_all, (int)all.size(), pl.nmax_all, st) != hipSuccess) return MH_EDEVICE;
+  } else {
+    // moments may have been replaced from the host: refresh the FP32 copies
+    if (launch_sync32(d_all, (int)all.size(), pl.nmax_all, (int)(o.k0 & 1), st) != hipSuccess)
+      return MH_EDEVICE;
+  }
+  const int64_t k0 = o.k0;
+  const int64_t k1 = o.k1 < 0 ? pl.kmax : std::min<int64_t>(o.k1, pl.kmax);
+  const bool any_res = !pl.res64.empty() || !pl.res32.empty();
+  const bool any_til = !pl.tasks64.empty() || !pl.tasks32.empty();
+  int tq = any_res && k1 > k0 ? timing_begin(c, st, 1) : -1;
+  if (launch_resident(true, d_res64, (int)pl.res64.size(), k0, k1, pl.nmax_res64, st) != hipSuccess)
+    return MH_EDEVICE;
+  if (launch_resident(false, d_res32, (int)pl.res32.size(), k0, k1, pl.nmax_res32, st) !=
+      hipSuccess)
+    return MH_EDEVICE;
+  timing_end(c, st, tq);
+  for (int64_t k = k0; k < k1 && any_til; ++k) {
+    tq = timing_begin(c, st, 0);
+    if (launch_tiled(true, d_til64, d_t64, (int)pl.tasks64.size(), part64, c->d_ctr.as<unsigned>(),
+                     k, st) != hipSuccess)
+      return MH_EDEVICE;
+    if (launch_tiled(false, d_til32, d_t32, (int)pl.tasks32.size(), part32,
+                     c->d_ctr.as<unsigned>(), k, st) != hipSuccess)
+      return MH_EDEVICE;
+    timing_end(c, st, tq);
+  }
+  (void)d_til64;
+  (void)d_til32;
+  if (o.finalize) {
+    if (launch_finalize(d_all, (int)all.size(), st) != hipSuccess) return MH_EDEVICE;
+    for (auto& f : fin) {
+      mh_asm* a = f.first;
+      if (launch_finalize_asm(a->sys_area.as<double>(), (int)a->R, a->stats.as<double>(), st) !=
+          hipSuccess)
+        return MH_EDEVICE;
+    }
+  }
+  for (auto& f : fin) {
+    mh_asm* a = f.first;
+    if (!a->done && hipEventCreateWithFlags(&a->done, hipEventDisableTiming) != hipSuccess)
+      return MH_EDEVICE;
+    if (hipEventRecord(a->done, st) != hipSuccess) return MH_EDEVICE;
+    a->ran = true;
+    a->state_parity = (int)(std::min<int64_t>(k1, total_steps(a->p)) & 1);
+  }
+  return MH_OK;
+}
+
+}  // namespace
+
+
+extern "C" {
+
+int mh_ctx_set_timing(mh_ctx* c, int on) {
+  if (!c) return MH_EINVAL;
+  if (set_dev(c)) return MH_EDEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return MH_EDEVICE;
+  c->timing = on ? 1 : 0;
+  c->ev_used = 0;
+  c->ev_kind.clear();
+  return MH_OK;
+}
+
+int mh_ctx_get_timing(mh_ctx* c, int32_t kind, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return MH_EINVAL;
+  if (set_dev(c)) return MH_EDEVICE;
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (size_t q = 0; q < c->ev_kind.size(); ++q) {
+    if (c->ev_kind[q] != kind) continue;
+    if (hipEventSynchronize(c->ev_pool[2 * q + 1]) != hipSuccess) return MH_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[2 * q], c->ev_pool[2 * q + 1]) != hipSuccess)
+      return MH_EDEVICE;
+    tot += ms;
+    ++cnt;
+  }
+  *total_ms = tot;
+  *launches = cnt;
+  c->ev_used = 0;
+  c->ev_kind.clear();
+  return MH_OK;
+}
+
+const char* mh_strerror(int code) {
+  switch (code) {
+    case MH_OK: return "ok";
+    case MH_EINVAL: return "invalid argument";
+    case MH_EOVERLAP: return "particles overlap";
+    case MH_ENOMEM: return "out of memory";
+    case MH_EDEVICE: return "HIP device error";
+    case MH_ENOTREADY: return "no finished run";
+    case MH_ENUMERIC: return "non-finite value";
+    case MH_EBUDGET: return "device-memory budget exceeded";
+    default: return "unknown error";
+  }
+}
+
+int mh_ctx_create(int device, mh_ctx** out) {
+  if (!out) return MH_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MH_EDEVICE;
+  mh_ctx* c = new (std::nothrow) mh_ctx();
+  if (!c) return MH_ENOMEM;
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&c->stream) != hipSuccess) {
+    delete c;
+    return MH_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
+  if (set_resident_lds_limit() != hipSuccess) {
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+    return MH_EDEVICE;
+  }
+  *out = c;
+  return MH_OK;
+}
+
+int mh_ctx_destroy(mh_ctx* c) {
+  if (!c) return MH_EINVAL;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  c->d_sys.release();
+  c->d_tasks.release();
+  c->d_part.release();
+  c->d_ctr.release();
+  c->h_stage.release();
+  (void)hipStreamDestroy(c->stream);
+  delete c;
+  return MH_OK;
+}
+
+int mh_create_assembly(mh_ctx* c, int64_t n, const double* pos, const double* axes,
+                       int64_t n_axes_sets, const mh_params* params, mh_asm** out) {
+  if (!out) return MH_EINVAL;
+  *out = nullptr;
+  if (!c || !pos || !axes || n < 1 || n > (1 << 24) || n_axes_sets < 1) return MH_EINVAL;
+  int e = validate_params(params);
+  if (e) return e;
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!std::isfinite(pos[i])) return MH_EINVAL;
+  std::vector<D4> ax((size_t)(n * n_axes_sets));
+  for (int64_t i = 0; i < n * n_axes_sets; ++i) {
+    const double x = axes[3 * i], y = axes[3 * i + 1], z = axes[3 * i + 2];
+    if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return MH_EINVAL;
+    const double nn = std::sqrt(x * x + y * y + z * z);
+    if (!(nn > 0)) return MH_EINVAL;
+    ax[i] = D4{x / nn, y / nn, z / nn, 0.0};
+  }
+  if ((e = check_overlap(n, pos, params->d))) return e;
+  if (set_dev(c)) return MH_EDEVICE;
+  mh_asm* a = new (std::nothrow) mh_asm();
+  if (!a) return MH_ENOMEM;
+  a->ctx = c;
+  a->n = n;
+  a->n_axes_sets = n_axes_sets;
+  a->p = *params;
+  std::vector<D4> p64((size_t)n);
+  std::vector<F4> p32((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    p64[i] = D4{pos[3 * i] / params->d, pos[3 * i + 1] / params->d, pos[3 * i + 2] / params->d, 0};
+    p32[i] = F4{(float)p64[i].x, (float)p64[i].y, (float)p64[i].z, 0.f};
+  }
+  if ((e = a->pos64.ensure(sizeof(D4) * n)) || (e = a->pos32.ensure(sizeof(F4) * n)) ||
+      (e = a->axes.ensure(sizeof(D4) * n * n_axes_sets))) {
+    mh_destroy_assembly(a);
+    return e;
+  }
+  if (hipMemcpy(a->pos64.p, p64.data(), sizeof(D4) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(a->pos32.p, p32.data(), sizeof(F4) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(a->axes.p, ax.data(), sizeof(D4) * n * n_axes_sets, hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    mh_destroy_assembly(a);
+    return MH_EDEVICE;
+  }
+  *out = a;
+  return MH_OK;
+}
+
+int mh_destroy_assembly(mh_asm* a) {
+  if (!a) return MH_EINVAL;
+  (void)hipSetDevice(a->ctx->device);
+  if (a->done) {
+    (void)hipEventSynchronize(a->done);
+    (void)hipEventDestroy(a->done);
+  }
+  DevBuf* bufs[] = {&a->pos64, &a->pos32, &a->axes, &a->m64, &a->m32, &a->area, &a->recpart,
+                    &a->rec, &a->sys_area, &a->stats, &a->diag, &a->tmp};
+  for (auto* b : bufs) b->release();
+  delete a;
+  return MH_OK;
+}
+
+int mh_run_batch(mh_asm* const* asms, int32_t count, const int64_t* n_replicas,
+                 const uint64_t* seeds, void* hip_stream) {
+  if (!asms || count < 1 || !n_replicas || !seeds) return MH_EINVAL;
+  std::vector<mh_asm*> v;
+  std::vector<int64_t> R;
+  std::vector<uint64_t> S;
+  for (int q = 0; q < count; ++q) {
+    if (!asms[q] || n_replicas[q] < 1 || n_replicas[q] > (1 << 20)) return MH_EINVAL;
+    for (int w = 0; w < q; ++w)
+      if (asms[w] == asms[q]) return MH_EINVAL;
+    v.push_back(asms[q]);
+    R.push_back(n_replicas[q]);
+    S.push_back(seeds[q]);
+  }
+  RunOpts o;
+  return run_systems(v, R, S, (hipStream_t)hip_stream, o);
+}
+
+int mh_run_loops(mh_asm* a, int64_t n_replicas, uint64_t seed, void* hip_stream) {
+  mh_asm* arr[1] = {a};
+  return mh_run_batch(arr, 1, &n_replicas, &seed, hip_stream);
+}
+
+int mh_sync(mh_asm* a) {
+  if (!a) return MH_EINVAL;
+  if (!a->ran || !a->done) return MH_ENOTREADY;
+  if (set_dev(a->ctx)) return MH_EDEVICE;
+  return hipEventSynchronize(a->done) == hipSuccess ? MH_OK : MH_EDEVICE;
+}
+
+int mh_get_loop(mh_asm* a, int64_t replica, int32_t period, double* H_T, double* M_Apm) {
+  if (!a || !H_T || !M_Apm) return MH_EINVAL;
+  int e = mh_sync(a);
+  if (e) return e;
+  if (replica < 0 || replica >= a->R || period < 0 || period >= n_kept(a->p)) return MH_EINVAL;
+  const int S = a->p.steps_per_period;
+  const int64_t rows = (int64_t)n_kept(a->p) * S;
+  if (hipMemcpy(M_Apm, a->rec.as<double>() + replica * rows + (int64_t)period * S,
+                sizeof(double) * S, hipMemcpyDeviceToHost) != hipSuccess)
+    return MH_EDEVICE;
+  const double scale = a->p.Ms / (double)a->n;
+  for (int k = 0; k < S; ++k) {
+    M_Apm[k] *= scale;
+    const int64_t kg = (int64_t)(a->p.n_discard + period) * S + k;
+    H_T[k] = a->p.dt_override > 0
+                 ? a->p.mu0Hmax
+                 : a->p.mu0Hmax * std::cos(2.0 * 3.14159265358979323846 * (double)kg / (double)S);
+  }
+  return MH_OK;
+}
+
+int mh_get_sar(mh_asm* a, double* sar_Wkg, double* sar_se, double* area_Jm3, double* area_se,
+               double* area_per_np) {
+  if (!a) return MH_EINVAL;
+  int e = mh_sync(a);
+  if (e) return e;
+  double st[2];
+  if (hipMemcpy(st, a->stats.p, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+    return MH_EDEVICE;
+  if (!std::isfinite(st[0]) || !std::isfinite(st[1])) return MH_ENUMERIC;
+  const double conv = a->p.f / a->p.rho;
+  if (sar_Wkg) *sar_Wkg = st[0] * conv;
+  if (sar_se) *sar_se = st[1] * conv;
+  if (area_Jm3) *area_Jm3 = st[0];
+  if (area_se) *area_se = st[1];
+  if (area_per_np) {
+    if ((e = a->tmp.ensure(sizeof(double) * a->n))) return e;
+    if (launch_area_per_np(a->area.as<double>(), (int)a->n, (int)a->R, n_kept(a->p),
+                           a->tmp.as<double>(), a->ctx->stream) != hipSuccess)
+      return MH_EDEVICE;
+    if (hipMemcpyAsync(area_per_np, a->tmp.p, sizeof(double) * a->n, hipMemcpyDeviceToHost,
+                       a->ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(a->ctx->stream) != hipSuccess)
+      return MH_EDEVICE;
+  }
+  return MH_OK;
+}
+
+int mh_get_replica_areas(mh_asm* a, double* area) {
+  if (!a || !area) return MH_EINVAL;
+  int e = mh_sync(a);
+  if (e) return e;
+  return hipMemcpy(area, a->sys_area.p, sizeof(double) * a->R, hipMemcpyDeviceToHost) ==
+                 hipSuccess
+             ? MH_OK
+             : MH_EDEVICE;
+}
+
+int mh_get_moments(mh_asm* a, int64_t replica, double* m) {
+  if (!a || !m) return MH_EINVAL;
+  int e = mh_sync(a);
+  if (e) return e;
+  if (replica < 0 || replica >= a->R) return MH_EINVAL;
+  // the state after the last executed step lives in buffer (steps & 1)
+  const int b = a->state_parity;
+  std::vector<D4> h((size_t)a->n);
+  if (hipMemcpy(h.data(), a->m64.as<D4>() + (int64_t)b * a->R * a->n + replica * a->n,
+                sizeof(D4) * a->n, hipMemcpyDeviceToHost) != hipSuccess)
+    return MH_EDEVICE;
+  for (int64_t i = 0; i < a->n; ++i) {
+    m[3 * i] = h[i].x;
+    m[3 * i + 1] = h[i].y;
+    m[3 * i + 2] = h[i].z;
+  }
+  return MH_OK;
+}
+
+int mh_debug_steps(mh_asm* a, int64_t n_replicas, uint64_t seed, int64_t k0, int64_t k1,
+                   const double* m_in, double* diag) {
+  if (!a || n_replicas < 1 || k0 < 0 || k1 < k0 || k1 > total_steps(a->p)) return MH_EINVAL;
+  if (a->p.precision == MH_BF16X3_WM) return MH_EINVAL;
+  if (set_dev(a->ctx)) return MH_EDEVICE;
+  std::vector<mh_asm*> v{a};
+  std::vector<int64_t> R{n_replicas};
+  std::vector<uint64_t> S{seed};
+  hipStream_t st = a->ctx->stream;
+  int e;
+  if (!a->ran || a->R != n_replicas || a->seed != seed) {
+    RunOpts o;
+    o.k0 = 0;
+    o.k1 = 0;
+    o.finalize = false;
+    if ((e = run_systems(v, R, S, st, o))) return e;
+  }
+  const int64_t n = a->n;
+  if (m_in) {
+    std::vector<D4> h((size_t)(n_replicas * n));
+    for (int64_t q = 0; q < n_replicas * n; ++q) {
+      const double x = m_in[3 * q], y = m_in[3 * q + 1], z = m_in[3 * q + 2];
+      if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z)) return MH_EINVAL;
+      h[q] = D4{x, y, z, 0.0};
+    }
+    if (hipStreamSynchronize(st) != hipSuccess ||
+        hipMemcpy(a->m64.as<D4>() + (k0 & 1) * n_replicas * n, h.data(), sizeof(D4) * h.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return MH_EDEVICE;
+  } else if (a->state_parity != (int)(k0 & 1)) {
+    return MH_EINVAL;
+  }
+  double* d_diag = nullptr;
+  if (diag) {
+    if ((e = a->diag.ensure(sizeof(double) * 8 * n_replicas * n))) return e;
+    d_diag = a->diag.as<double>();
+  }
+  RunOpts o;
+  o.init = false;
+  o.k0 = k0;
+  o.k1 = k1;
+  o.finalize = false;
+  o.diag = d_diag;
+  if ((e = run_systems(v, R, S, st, o))) return e;
+  a->state_parity = (int)(k1 & 1);
+  if (hipStreamSynchronize(st) != hipSuccess) return MH_EDEVICE;
+  if (diag && hipMemcpy(diag, d_diag, sizeof(double) * 8 * n_replicas * n,
+                        hipMemcpyDeviceToHost) != hipSuccess)
+    return MH_EDEVICE;
+  return MH_OK;
+}
+
+int mh_debug_field(mh_asm* a, const double* m, double* B_out) {
+  if (!a || !m || !B_out) return MH_EINVAL;
+  if (a->p.precision == MH_BF16X3_WM) return MH_EINVAL;
+  if (set_dev(a->ctx)) return MH_EDEVICE;
+  const int64_t n = a->n;
+  std::vector<mh_asm*> v{a};
+  std::vector<int64_t> R{1};
+  std::vector<uint64_t> S{0};
+  hipStream_t st = a->ctx->stream;
+  RunOpts o0;
+  o0.k0 = 0;
+  o0.k1 = 0;
+  o0.finalize = false;
+  int e;
+  if ((e = run_systems(v, R, S, st, o0))) return e;
+  std::vector<D4> h((size_t)n);
+  for (int64_t q = 0; q < n; ++q) h[q] = D4{m[3 * q], m[3 * q + 1], m[3 * q + 2], 0.0};
+  if ((e = a->diag.ensure(sizeof(double) * 8 * n))) return e;
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(a->m64.p, h.data(), sizeof(D4) * n, hipMemcpyHostToDevice) != hipSuccess)
+    return MH_EDEVICE;
+  RunOpts o;
+  o.init = false;
+  o.k0 = 0;
+  o.k1 = 1;
+  o.finalize = false;
+  o.field_only = true;
+  o.diag = a->diag.as<double>();
+  if ((e = run_systems(v, R, S, st, o))) return e;
+  a->state_parity = 0;
+  std::vector<double> d((size_t)(8 * n));
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(d.data(), a->diag.p, sizeof(double) * 8 * n, hipMemcpyDeviceToHost) != hipSuccess)
+    return MH_EDEVICE;
+  for (int64_t q = 0; q < n; ++q)
+    for (int c = 0; c < 3; ++c) B_out[3 * q + c] = d[8 * q + c];
+  return MH_OK;
+}
+
+int mh_debug_philox(mh_ctx* c, uint64_t seed, uint64_t stream, int64_t n_blocks,
+                    const uint64_t* ctr, uint64_t* out) {
+  if (!c || !ctr || !out || n_blocks < 1 || n_blocks > (1 << 26)) return MH_EINVAL;
+  if (set_dev(c)) return MH_EDEVICE;
+  void *dc = nullptr, *dout = nullptr;
+  const size_t bytes = sizeof(uint64_t) * 4 * n_blocks;
+  int rc = MH_OK;
+  if (hipMalloc(&dc, bytes) != hipSuccess || hipMalloc(&dout, bytes) != hipSuccess) {
+    rc = MH_ENOMEM;
+  } else if (hipMemcpy(dc, ctr, bytes, hipMemcpyHostToDevice) != hipSuccess ||
+             launch_philox_raw(seed, stream, (const uint64_t*)dc, (uint64_t*)dout, n_blocks,
+                               c->stream) != hipSuccess ||
+             hipStreamSynchronize(c->stream) != hipSuccess ||
+             hipMemcpy(out, dout, bytes, hipMemcpyDeviceToHost) != hipSuccess) {
+    rc = MH_EDEVICE;
+  }
+  if (dc) (void)hipFree(dc);
+  if (dout) (void)hipFree(dout);
+  return rc;
+}
+
+int mh_debug_sw(mh_ctx* c, int64_t n, const double* hx, const double* hy, const double* theta0,
+                double* out) {
+  if (!c || !hx || !hy || !theta0 || !out || n < 1 || n > (1 << 26)) return MH_EINVAL;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || !(hy[i] >= 0) ||
+        !(std::fabs(theta0[i]) <= 3.14159265358979323846))
+      return MH_EINVAL;
+  if (set_dev(c)) return MH_EDEVICE;
+  double* d = nullptr;
+  const size_t in = sizeof(double) * n;
+  int rc = MH_OK;
+  if (hipMalloc(&d, in * 9) != hipSuccess) return MH_ENOMEM;
+  if (hipMemcpy(d, hx, in, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d + n, hy, in, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d + 2 * n, theta0, in, hipMemcpyHostToDevice) != hipSuccess ||
+      launch_sw(d, d + n, d + 2 * n, d + 3 * n, n, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess ||
+      hipMemcpy(out, d + 3 * n, in * 6, hipMemcpyDeviceToHost) != hipSuccess)
+    rc = MH_EDEVICE;
+  (void)hipFree(d);
+  return rc;
+}
+
+}  // extern "C"

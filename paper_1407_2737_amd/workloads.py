@@ -204,7 +204,7 @@ def config2(mu0Hmax: float = 0.02, n_periods: int = 5) -> Assembly:
     n, R, d = 5000, 250e-9, 12e-9
     pos = place_random(n, R, d, 1000 + c)
     ax = axes_random_3d(n, 2000 + c)
-    mat = Material(d=d, mu0Hmax=mu0Hmax, n_periods=n_periods, n_discard=1)
+    mat = Material(d=d, mu0Hmax=mu0Hmax, n_periods=n_periods, n_discard=min(1, n_periods - 1))
     return Assembly(pos, ax, mat, R, 3000 + c, {"phi": volume_fraction(n, R, d)})
 
 
