@@ -89,6 +89,7 @@ def main():
         res = one_run()
     t1 = time.perf_counter()
     ms_kernel, launches = ctx.get_timing(0)
+    ms_update, launches_u = ctx.get_timing(3)
     ctx.set_timing(False)
     wall = t1 - t0
     np_steps = n_total * steps_per_run * args.steps
@@ -98,8 +99,9 @@ def main():
     achieved = FLOPS_PER_PAIR * pairs_per_launch / avg_launch_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-                "kernel": "k_tiled<float,256>", "avg_launch_us": avg_launch_s * 1e6,
-                "launches": launches}
+                "kernel": "k_field<float>", "avg_launch_us": avg_launch_s * 1e6,
+                "launches": launches,
+                "update_kernel_avg_us": ms_update * 1e3 / max(launches_u, 1)}
     line = {
         "metric": "NP·steps/s (dipolar+kMC)",
         "value": value,

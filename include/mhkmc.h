@@ -149,9 +149,9 @@ int mh_debug_field(mh_asm* a, const double* m, double* B_out);
 
 /* Launch timing (diagnostics for roofline reports). When on, every step-kernel launch
  * is bracketed by a pair of HIP events on the stream it runs on. mh_ctx_get_timing
- * waits for the recorded launches of one kind (0: tiled field+update step, 1: resident
- * whole-run launch, 2: interaction-matrix step), returns their summed duration (ms) and
- * count, and clears the record. */
+ * waits for the recorded launches of one kind (0: tiled dipolar-field kernel, 1: resident
+ * whole-run launch, 2: interaction-matrix step, 3: per-particle update kernel), returns
+ * their summed duration (ms) and count. mh_ctx_set_timing clears the record. */
 int mh_ctx_set_timing(mh_ctx* ctx, int on);
 int mh_ctx_get_timing(mh_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
 

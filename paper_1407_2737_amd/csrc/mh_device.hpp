@@ -84,25 +84,93 @@ __device__ __forceinline__ double sw_gp(double t, double hx, double hy, double& 
   return (c * c - s * s) + hx * c + hy * s;
 }
 
-// Zero of f on (a, b) where f(a) < 0 iff a_neg; Newton kept inside the bracket.
+// FP32 seed of a zero of g (kDeriv = false) or of g' (kDeriv = true) on (a, b), where the
+// function is negative at a iff a_neg: Newton kept inside the bracket, bisection when a
+// step leaves it. Accurate to the single-precision sine/cosine (about 1e-6).
 template <bool kDeriv>
-__device__ double bracketed_root(double a, double b, bool a_neg, double hx, double hy) {
-  double x = 0.5 * (a + b);
+__device__ float seed_root(float a, float b, bool a_neg, float hx, float hy) {
+  float x = 0.5f * (a + b);
+  for (int it = 0; it < 30; ++it) {
+    float s, c;
+    __sincosf(x, &s, &c);
+    float f, d;
+    if (kDeriv) {
+      f = (c * c - s * s) + hx * c + hy * s;
+      d = -4.f * s * c - hx * s + hy * c;
+    } else {
+      f = s * c + hx * s - hy * c;
+      d = (c * c - s * s) + hx * c + hy * s;
+    }
+    if ((f < 0.f) == a_neg)
+      a = x;
+    else
+      b = x;
+    const float dx = -f / d;
+    if (fabsf(dx) < 1e-6f) break;  // converged to single precision
+    float xn = x + dx;
+    if (!(xn > a && xn < b)) xn = 0.5f * (a + b);
+    x = xn;
+  }
+  return x;
+}
+
+// FP64 zero of g / g' on the FP64 bracket (a, b), started from x0. Newton steps rotate
+// the pair (sin x, cos x) by the step with a short Taylor series once the step is below
+// 1e-3, so a converged polish costs one double-precision sincos. Returns the root and
+// its sine and cosine.
+template <bool kDeriv>
+__device__ double polish_root(double a, double b, bool a_neg, double hx, double hy, double x0,
+                              double& s_out, double& c_out) {
+  double x = (x0 > a && x0 < b) ? x0 : 0.5 * (a + b);
+  double s, c;
+  sincos(x, &s, &c);
   for (int it = 0; it < 200; ++it) {
-    double d;
-    const double f = kDeriv ? sw_gp(x, hx, hy, d) : sw_g(x, hx, hy, d);
-    if (f == 0.0) return x;
+    double f, d;
+    if (kDeriv) {
+      f = (c * c - s * s) + hx * c + hy * s;
+      d = -4.0 * s * c - hx * s + hy * c;
+    } else {
+      f = s * c + hx * s - hy * c;
+      d = (c * c - s * s) + hx * c + hy * s;
+    }
+    if (f == 0.0) break;
     if ((f < 0.0) == a_neg)
       a = x;
     else
       b = x;
-    double xn = x - f / d;
-    if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
-    const double step = fabs(xn - x);
+    const double dx = -f / d;
+    if (fabs(dx) <= 2e-16 * fmax(1.0, fabs(x))) break;  // converged: x is the root
+    double xn = x + dx;
+    if (!(xn > a && xn < b)) {  // bisect
+      xn = 0.5 * (a + b);
+      if (xn == a || xn == b) break;
+      x = xn;
+      sincos(x, &s, &c);
+      continue;
+    }
+    if (fabs(dx) < 1e-3) {
+      const double d2 = dx * dx;
+      const double cd = 1.0 - d2 * (0.5 - d2 * (1.0 / 24.0 - d2 * (1.0 / 720.0)));
+      const double sd = dx * (1.0 - d2 * (1.0 / 6.0 - d2 * (1.0 / 120.0 - d2 * (1.0 / 5040.0))));
+      const double cn = c * cd - s * sd;
+      s = s * cd + c * sd;
+      c = cn;
+    } else {
+      sincos(xn, &s, &c);
+    }
     x = xn;
-    if (step <= 1e-15 * fmax(1.0, fabs(x)) || (b - a) <= 4e-16 * fmax(1.0, fabs(x))) break;
+    if (fabs(dx) <= 2e-16 * fmax(1.0, fabs(x)) || (b - a) <= 4e-16 * fmax(1.0, fabs(x))) break;
   }
+  s_out = s;
+  c_out = c;
   return x;
+}
+
+template <bool kDeriv>
+__device__ __forceinline__ double find_root(double a, double b, bool a_neg, double hx, double hy,
+                                            double& s, double& c) {
+  const float x0 = seed_root<kDeriv>((float)a, (float)b, a_neg, (float)hx, (float)hy);
+  return polish_root<kDeriv>(a, b, a_neg, hx, hy, (double)x0, s, c);
 }
 
 __device__ __forceinline__ double wrap_pi(double t) {
@@ -119,6 +187,7 @@ __device__ __forceinline__ bool astroid_bistable(double hx, double hy) {
 
 struct SWState {
   double th_c, e_c, th_o, e_o, e3;  // current/other minimum, lower maximum (units K V)
+  double s_c, c_c, s_o, c_o;        // sine and cosine of th_c and th_o
   bool two;
 };
 
@@ -151,6 +220,9 @@ __device__ SWState sw_fall(double hx, double hy, double theta0) {
       r.e_c = r.e_o = hx > 0.0 ? e0 : epi;
       r.e3 = 0.0;
     }
+    r.s_c = r.s_o = 0.0;
+    r.c_c = r.th_c == 0.0 ? 1.0 : -1.0;
+    r.c_o = r.th_o == 0.0 ? 1.0 : -1.0;
     return r;
   }
   if (hx == 0.0) {
@@ -165,74 +237,97 @@ __device__ SWState sw_fall(double hx, double hy, double theta0) {
       r.th_o = toa ? kPi - a : a;
       r.e_c = r.e_o = em;
       r.e3 = 1.0 - 2.0 * hy;
+      const double ca = sqrt((1.0 - hy) * (1.0 + hy));
+      r.s_c = r.s_o = hy;
+      r.c_c = toa ? ca : -ca;
+      r.c_o = toa ? -ca : ca;
     } else {
       r.two = false;
       r.th_c = r.th_o = kHalfPi;
       r.e_c = r.e_o = 1.0 - 2.0 * hy;
       r.e3 = 0.0;
+      r.s_c = r.s_o = 1.0;
+      r.c_c = r.c_o = 0.0;
     }
     return r;
   }
   // ---- general case: reflect into hx > 0 ----
   const bool refl = hx < 0.0;
   const double ax = fabs(hx);
-  const double r1 = bracketed_root<false>(0.0, kHalfPi, true, ax, hy);        // global min
-  const double r3 = bracketed_root<false>(kPi, 1.5 * kPi, false, ax, hy);     // global max
-  double s, c;
-  sincos(r1, &s, &c);
-  const double e1 = sw_energy(s, c, ax, hy);
+  double s1, c1;
+  const double r1 = find_root<false>(0.0, kHalfPi, true, ax, hy, s1, c1);  // global minimum
+  const double e1 = sw_energy(s1, c1, ax, hy);
   bool two = false;
-  double r2a = 0.0, r2b = 0.0, e2a = 0.0, e2b = 0.0;
+  double r2a = 0.0, r2b = 0.0, e2a = 0.0, e2b = 0.0, s2 = 0.0, c2 = 0.0;
   if (astroid_bistable(ax, hy)) {
-    const double ts = bracketed_root<true>(kHalfPi, kPi, true, ax, hy);
-    double d;
-    if (sw_g(ts, ax, hy, d) < 0.0) {
+    // the zero t* of g' in (pi/2, pi) separates the saddle maximum and the metastable
+    // minimum; the single-precision t* is used when g < 0 there in double precision
+    double ts = (double)seed_root<true>((float)kHalfPi, (float)kPi, true, (float)ax, (float)hy);
+    if (!(ts > kHalfPi && ts < kPi)) ts = 0.5 * (kHalfPi + kPi);
+    double st, ct;
+    sincos(ts, &st, &ct);
+    if (!(st * ct + ax * st - hy * ct < 0.0)) ts = polish_root<true>(kHalfPi, kPi, true, ax, hy, ts, st, ct);
+    if (st * ct + ax * st - hy * ct < 0.0) {
       two = true;
-      r2a = bracketed_root<false>(kHalfPi, ts, false, ax, hy);  // saddle maximum
-      r2b = bracketed_root<false>(ts, kPi, true, ax, hy);       // metastable minimum
-      sincos(r2a, &s, &c);
-      e2a = sw_energy(s, c, ax, hy);
-      sincos(r2b, &s, &c);
-      e2b = sw_energy(s, c, ax, hy);
+      double sa, ca;
+      r2a = find_root<false>(kHalfPi, ts, false, ax, hy, sa, ca);  // saddle maximum
+      r2b = find_root<false>(ts, kPi, true, ax, hy, s2, c2);       // metastable minimum
+      e2a = sw_energy(sa, ca, ax, hy);
+      e2b = sw_energy(s2, c2, ax, hy);
     }
   }
+  // back to the unreflected frame: theta = pi - theta_r flips the cosine
   const double back1 = refl ? wrap_pi(kPi - r1) : r1;
+  r.s_c = s1;
+  r.c_c = refl ? -c1 : c1;
   if (!two) {
     r.two = false;
     r.th_c = r.th_o = back1;
     r.e_c = r.e_o = e1;
     r.e3 = 0.0;
+    r.s_o = r.s_c;
+    r.c_o = r.c_c;
     return r;
   }
-  sincos(r3, &s, &c);
-  const double e3g = sw_energy(s, c, ax, hy);
-  const double e3 = fmin(e2a, e3g);
-  // basin of theta0 in the reflected frame: the circle reads r1 (min) < r2a (max)
-  // < r2b (min) < r3 (max) < r1 + 2 pi
-  double x = refl ? (kPi - theta0) : theta0;
-  // into [r3 - 2 pi, r3): theta0 lies in [-pi, pi], so one correction either way suffices
-  if (x >= r3) x -= 2.0 * kPi;
-  if (x < r3 - 2.0 * kPi) x += 2.0 * kPi;
-  bool to1;
-  if (x == r2a || x == r3 - 2.0 * kPi) {
-    if (e1 != e2b) {
-      to1 = e1 < e2b;
-    } else {
-      const double th1 = back1, th2 = refl ? wrap_pi(kPi - r2b) : wrap_pi(r2b);
-      const double d1 = fabs(wrap_pi(theta0 - th1)), d2 = fabs(wrap_pi(theta0 - th2));
-      to1 = (d1 < d2) || (d1 == d2 && th1 <= th2);
-    }
-  } else {
-    to1 = x < r2a;
+  // basin of theta0. In the reflected frame the circle reads r1 (min) < r2a (max) <
+  // r2b (min) < r3 (max) < r1 + 2 pi, with r3 the global maximum in (pi, 3 pi / 2);
+  // r3 is only needed when the moment lies in that quadrant.
+  double y = refl ? (kPi - theta0) : theta0;
+  if (y >= 1.5 * kPi) y -= 2.0 * kPi;
+  if (y < -kHalfPi) y += 2.0 * kPi;
+  int basin;  // 1: r1, 2: r2b, 0: on a maximum
+  if (y < r2a)
+    basin = 1;
+  else if (y == r2a)
+    basin = 0;
+  else if (y <= kPi)
+    basin = 2;
+  else {
+    double s3, c3;
+    const double r3 = find_root<false>(kPi, 1.5 * kPi, false, ax, hy, s3, c3);
+    basin = y < r3 ? 2 : (y > r3 ? 1 : 0);
   }
-  const double b1 = back1;
   const double b2 = refl ? wrap_pi(kPi - r2b) : wrap_pi(r2b);
+  if (basin == 0) {
+    if (e1 != e2b) {
+      basin = e1 < e2b ? 1 : 2;
+    } else {
+      const double d1 = fabs(wrap_pi(theta0 - back1)), d2 = fabs(wrap_pi(theta0 - b2));
+      basin = ((d1 < d2) || (d1 == d2 && back1 <= b2)) ? 1 : 2;
+    }
+  }
+  const bool to1 = basin == 1;
+  const double s2u = s2, c2u = refl ? -c2 : c2;
   r.two = true;
-  r.th_c = to1 ? b1 : b2;
+  r.th_c = to1 ? back1 : b2;
   r.e_c = to1 ? e1 : e2b;
-  r.th_o = to1 ? b2 : b1;
+  r.th_o = to1 ? b2 : back1;
   r.e_o = to1 ? e2b : e1;
-  r.e3 = e3;
+  r.e3 = e2a;
+  r.s_c = to1 ? s1 : s2u;
+  r.c_c = to1 ? (refl ? -c1 : c1) : c2u;
+  r.s_o = to1 ? s2u : s1;
+  r.c_o = to1 ? c2u : (refl ? -c1 : c1);
   return r;
 }
 
@@ -316,7 +411,7 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
   const double theta0 = atan2(mx * ux + my * uy + mz * uz, mx * nx + my * ny + mz * nz);
   // steps iv-v
   const SWState sw = sw_fall(hx, hy, theta0);
-  double th = sw.th_c;
+  double s = sw.s_c, c = sw.c_c;
   out.two = sw.two;
   // steps vi-vii
   if (p.thermal && sw.two) {
@@ -332,12 +427,11 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
     const double u = philox_uniform(seed, stream, i, k);
     out.P = P;
     if (u < P) {
-      th = sw.th_o;
+      s = sw.s_o;
+      c = sw.c_o;
       out.jump = 1;
     }
   }
-  double s, c;
-  sincos(th, &s, &c);
   out.mx = c * nx + s * ux;
   out.my = c * ny + s * uy;
   out.mz = c * nz + s * uz;

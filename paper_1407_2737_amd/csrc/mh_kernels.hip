@@ -12,10 +12,9 @@
 // Two launch forms of the same step:
 //   k_resident  one workgroup owns a whole small system and runs every step in one
 //               launch, positions and field-side moments resident in LDS;
-//   k_tiled     one launch per step over (system, i-tile, j-chunk) blocks; j-chunks
-//               are staged through LDS, partial fields are written to a buffer and
-//               the last block of an i-tile (device-scope counter) sums them in fixed
-//               order and runs the per-particle update.
+//   k_field +   two launches per step: the dipolar sums over (system, i-tile) blocks
+//   k_update    with sources staged through LDS, then one thread per particle for
+//               the per-particle update.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -207,80 +206,101 @@ __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ sy
 }
 
 // ---------------------------------------------------------------------------
-// Tiled form, one launch per step k. 256 targets per block (one per thread), a
-// chunk of JC sources staged through LDS.
+// Tiled form: two launches per step k.
+//
+// k_field over (system, i-tile) blocks of 1024 threads. A block owns TI targets; its
+// 16 waves split the sources into Q = 16 * 64 / TI interleaved streams (lane l of wave
+// w: target l % TI, stream w * (64/TI) + l / TI). Sources are staged through LDS in
+// chunks of CH; partial fields are reduced across streams in LDS in a fixed order in
+// FP64 and written per particle. No block depends on another.
+//
+// k_update, one thread per particle: steps iii-vii and the accumulations.
 // ---------------------------------------------------------------------------
-template <typename T, int JC>
-__global__ __launch_bounds__(256) void k_tiled(const SysDesc* __restrict__ systems,
-                                               const Task* __restrict__ tasks,
-                                               typename V4<T>::type* __restrict__ part,
-                                               unsigned int* __restrict__ counters, int64_t k) {
+template <typename T, int TI>
+__global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ systems,
+                                                const int2* __restrict__ tiles, int64_t k) {
   using P4 = typename V4<T>::type;
-  __shared__ P4 spos[JC];
-  __shared__ P4 smom[JC];
-  __shared__ double red[4];
-  __shared__ int last;
-  const Task t = tasks[blockIdx.x];
-  const SysDesc& s = systems[t.sys];
+  constexpr int L = 64 / TI;      // streams per wave
+  constexpr int Q = 16 * L;       // streams per block
+  constexpr int CH = 1024;        // sources per staged chunk
+  __shared__ P4 spos[CH];
+  __shared__ P4 smom[CH];
+  __shared__ T red[3][Q][TI];
+  const int2 tl = tiles[blockIdx.x];
+  const SysDesc& s = systems[tl.x];
   if (k >= s.total_steps) return;
   const int n = s.n;
   const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63;
+  const int il = l % TI;
+  const int q = w * L + l / TI;
+  const int i = tl.y * TI + il;
   const int cur = (int)(k & 1);
   const P4* gpos = pos_of<T>(s);
   const P4* gmom = mom_of<T>(s) + (int64_t)cur * s.stride;
-  const int j0 = t.chunk * JC;
-  const int jn = min(JC, n - j0);
-  for (int j = tid; j < JC; j += 256) {
-    P4 p, m;
-    if (j < jn) {
-      p = gpos[j0 + j];
-      m = gmom[j0 + j];
-    } else {  // padding: far away and without moment, contributes exactly zero
-      p.x = p.y = p.z = (T)1e15;
-      m.x = m.y = m.z = (T)0;
-      p.w = m.w = (T)0;
-    }
-    spos[j] = p;
-    smom[j] = m;
-  }
-  __syncthreads();
-  const int i = t.itile * 256 + tid;
   T bx = 0, by = 0, bz = 0;
-  if (i < n) {
-    const P4 pi = gpos[i];
+  if (s.Bscale != 0.0 && n > 1) {
+    const P4 pi = gpos[i < n ? i : n - 1];
     const T xi = (T)pi.x, yi = (T)pi.y, zi = (T)pi.z;
-#pragma unroll 8
-    for (int j = 0; j < JC; ++j) dip_pair<T>(xi, yi, zi, spos[j], smom[j], bx, by, bz);
+    for (int c0 = 0; c0 < n; c0 += CH) {
+      const int cn = min(CH, n - c0);
+      __syncthreads();
+      for (int j = tid; j < CH; j += 1024) {
+        P4 p, m;
+        if (j < cn) {
+          p = gpos[c0 + j];
+          m = gmom[c0 + j];
+        } else {  // padding: far away and without moment, contributes exactly zero
+          p.x = p.y = p.z = (T)1e15;
+          m.x = m.y = m.z = (T)0;
+          p.w = m.w = (T)0;
+        }
+        spos[j] = p;
+        smom[j] = m;
+      }
+      __syncthreads();
+      const int ce = (cn + Q - 1) / Q * Q;  // streams stay in lockstep over padded entries
+#pragma unroll 4
+      for (int e = q; e < ce; e += Q) dip_pair<T>(xi, yi, zi, spos[e], smom[e], bx, by, bz);
+    }
   }
-  P4 pr;
-  pr.x = bx;
-  pr.y = by;
-  pr.z = bz;
-  pr.w = 0;
-  part[t.part_off + (int64_t)t.chunk * 256 + tid] = pr;
-  __threadfence();
+  red[0][q][il] = bx;
+  red[1][q][il] = by;
+  red[2][q][il] = bz;
   __syncthreads();
-  if (tid == 0) {
-    const unsigned prev = atomicAdd(&counters[t.tile_id], 1u);
-    last = (prev == (unsigned)(t.nchunks - 1));
+  if (tid < TI && i < n) {
+    double ax = 0, ay = 0, az = 0;
+    for (int qq = 0; qq < Q; ++qq) {
+      ax += (double)red[0][qq][tid];
+      ay += (double)red[1][qq][tid];
+      az += (double)red[2][qq][tid];
+    }
+    D4 f;
+    f.x = ax;
+    f.y = ay;
+    f.z = az;
+    f.w = 0.0;
+    s.field[i] = f;
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double ax = 0, ay = 0, az = 0;
-  for (int c = 0; c < t.nchunks; ++c) {
-    const P4 q = part[t.part_off + (int64_t)c * 256 + tid];
-    ax += (double)q.x;
-    ay += (double)q.y;
-    az += (double)q.z;
-  }
+}
+
+__global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ systems,
+                                                const int2* __restrict__ blocks, int64_t k) {
+  __shared__ double red[4];
+  const int2 bl = blocks[blockIdx.x];
+  const SysDesc& s = systems[bl.x];
+  if (k >= s.total_steps) return;
+  const int i = bl.y * 256 + threadIdx.x;
+  const int cur = (int)(k & 1);
   double mx = 0.0;
-  if (i < n) mx = np_epilogue(s, i, k, cur, ax, ay, az);
+  if (i < s.n) {
+    const D4 f = s.field[i];
+    mx = np_epilogue(s, i, k, cur, f.x, f.y, f.z);
+  }
   if (k >= s.kept0 && !s.field_only) {
     const double tot = block_sum_256(mx, red);
-    if (tid == 0) s.recpart[(k - s.kept0) * s.ntiles + t.itile] = tot;
+    if (threadIdx.x == 0) s.recpart[(k - s.kept0) * s.ntiles + bl.y] = tot;
   }
-  if (tid == 0) counters[t.tile_id] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -434,18 +454,30 @@ hipError_t set_resident_lds_limit() {
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
 }
 
-constexpr int kJC = 256;
-int tiled_chunk() { return kJC; }
+int tile_width(int kind) { return kind == 0 ? 64 : 16; }
 
-hipError_t launch_tiled(bool fp64, const SysDesc* d_sys, const Task* d_tasks, int ntasks,
-                        void* d_part, unsigned* d_ctr, int64_t k, hipStream_t st) {
-  if (ntasks == 0) return hipSuccess;
-  if (fp64)
-    hipLaunchKernelGGL((k_tiled<double, kJC>), dim3(ntasks), dim3(256), 0, st, d_sys, d_tasks,
-                       (D4*)d_part, d_ctr, k);
-  else
-    hipLaunchKernelGGL((k_tiled<float, kJC>), dim3(ntasks), dim3(256), 0, st, d_sys, d_tasks,
-                       (F4*)d_part, d_ctr, k);
+// kind 0: 64 targets per field block, kind 1: 16 targets per field block
+hipError_t launch_field(bool fp64, int kind, const SysDesc* d_sys, const int2* d_tiles, int ntiles,
+                        int64_t k, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  if (fp64) {
+    if (kind == 0)
+      hipLaunchKernelGGL((k_field<double, 64>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, k);
+    else
+      hipLaunchKernelGGL((k_field<double, 16>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, k);
+  } else {
+    if (kind == 0)
+      hipLaunchKernelGGL((k_field<float, 64>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, k);
+    else
+      hipLaunchKernelGGL((k_field<float, 16>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, k);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks, int64_t k,
+                         hipStream_t st) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, k);
   return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ struct SysDesc {
   double* area;      // per-particle area accumulators: [n] sums then [n] compensations
   double* recpart;   // loop record partial sums [n_kept * S][ntiles]
   double* diag;      // optional per-particle diagnostics (8 doubles each) or null
+  D4* field;         // reduced dipolar sum per particle, written by the field kernel
   double* rec;       // loop record of the kept steps: sum_i m_x after each step
   double* sys_area;  // this system's loop area (J/m^3), written at the end of a run
   int64_t stride;    // distance between the two moment buffers (elements)
@@ -33,18 +34,10 @@ struct SysDesc {
   double Bscale;     // mu0 Ms / 24: field unit of the reduced dipolar sum (T)
   double Ms;
   int32_t n;
-  int32_t ntiles;    // i-tiles of the tiled kernel (1 for the resident kernel)
+  int32_t ntiles;    // update blocks of 256 particles (1 for the resident kernel)
   int32_t S, total_steps, kept0, static_field;
   int32_t field_only;  // diagnostics: write the dipolar field to diag, change nothing
   int32_t pad_;
-};
-
-// One block of the tiled step: (system, i-tile, j-chunk)
-struct Task {
-  int32_t sys, itile, chunk, nchunks;
-  int64_t part_off;  // offset of this (system, i-tile) in the partial-sum buffer (F4/D4 units)
-  int32_t tile_id;   // counter index
-  int32_t pad;
 };
 
 __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {

@@ -20,9 +20,11 @@ hipError_t launch_resident(bool fp64, const SysDesc* d_sys, int nsys, int64_t k0
                            int nmax, hipStream_t st);
 size_t resident_lds_bytes(bool fp64, int nmax);
 hipError_t set_resident_lds_limit();
-int tiled_chunk();
-hipError_t launch_tiled(bool fp64, const SysDesc* d_sys, const Task* d_tasks, int ntasks,
-                        void* d_part, unsigned* d_ctr, int64_t k, hipStream_t st);
+int tile_width(int kind);
+hipError_t launch_field(bool fp64, int kind, const SysDesc* d_sys, const int2* d_tiles, int ntiles,
+                        int64_t k, hipStream_t st);
+hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks, int64_t k,
+                         hipStream_t st);
 hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st);
 hipError_t launch_init(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st);
 hipError_t launch_sync32(const SysDesc* d_sys, int nsys, int nmax, int b, hipStream_t st);
@@ -113,7 +115,8 @@ struct mh_asm {
   bool ran = false;
   int ntiles = 1;
   int resident = 0;
-  DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp;
+  int tile_kind = 0;  // 0: 64 targets per block, 1: 16
+  DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp, field;
   int state_parity = 0;  // the current moments live in buffer state_parity
   hipEvent_t done = nullptr;
   // host copy of the per-run system descriptors (for diagnostics re-runs)
@@ -192,12 +195,11 @@ bool wants_resident(const mh_asm* a, int64_t nsys_total) {
 }
 
 // (Re)allocate a replica set and its per-run buffers.
-int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident) {
+int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kind) {
   const int64_t n = a->n;
-  const int JC = tiled_chunk();
   a->resident = resident ? 1 : 0;
+  a->tile_kind = tile_kind;
   a->ntiles = resident ? 1 : (int)((n + 255) / 256);
-  (void)JC;
   const int64_t rows = (int64_t)n_kept(a->p) * a->p.steps_per_period;
   int e;
   if ((e = a->m64.ensure(sizeof(D4) * 2 * R * n))) return e;
@@ -207,6 +209,7 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident) {
   if ((e = a->rec.ensure(sizeof(double) * R * rows + 8))) return e;
   if ((e = a->sys_area.ensure(sizeof(double) * R))) return e;
   if ((e = a->stats.ensure(sizeof(double) * 4))) return e;
+  if (!resident && (e = a->field.ensure(sizeof(D4) * R * n))) return e;
   a->R = R;
   a->seed = seed;
   return MH_OK;
@@ -225,6 +228,7 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   const int64_t rows = (int64_t)n_kept(p) * p.steps_per_period;
   s.recpart = a->recpart.as<double>() + r * rows * a->ntiles;
   s.rec = a->rec.as<double>() + r * rows;
+  s.field = a->resident ? nullptr : a->field.as<D4>() + r * n;
   s.sys_area = a->sys_area.as<double>() + r;
   s.diag = nullptr;
   s.stride = a->R * n;
@@ -253,36 +257,23 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
 }
 
 struct Plan {
-  std::vector<SysDesc> res64, res32, til64, til32;
-  std::vector<Task> tasks64, tasks32;
+  std::vector<SysDesc> res64, res32, til[2][2];  // til[fp64][kind]
+  std::vector<int2> tiles[2][2];
+  std::vector<SysDesc> upd;   // all tiled systems
+  std::vector<int2> ublocks;  // (system in upd, block of 256 particles)
   int nmax_res64 = 0, nmax_res32 = 0;
-  int64_t part64 = 0, part32 = 0;  // partial-sum entries
-  int nctr = 0;
   int64_t kmax = 0;
   int nmax_all = 0;
 };
 
-void add_tiled(Plan& pl, std::vector<SysDesc>& sys, std::vector<Task>& tasks, int64_t& part,
-               const SysDesc& s) {
-  const int JC = tiled_chunk();
-  const int sidx = (int)sys.size();
-  sys.push_back(s);
-  const int nch = (s.n + JC - 1) / JC;
-  for (int it = 0; it < s.ntiles; ++it) {
-    const int64_t off = part;
-    part += (int64_t)nch * 256;
-    const int tid = pl.nctr++;
-    for (int c = 0; c < nch; ++c) {
-      Task t{};
-      t.sys = sidx;
-      t.itile = it;
-      t.chunk = c;
-      t.nchunks = nch;
-      t.part_off = off;
-      t.tile_id = tid;
-      tasks.push_back(t);
-    }
-  }
+void add_tiled(Plan& pl, int fp64, int kind, const SysDesc& s) {
+  const int sidx = (int)pl.til[fp64][kind].size();
+  pl.til[fp64][kind].push_back(s);
+  const int TI = tile_width(kind);
+  for (int it = 0; it < (s.n + TI - 1) / TI; ++it) pl.tiles[fp64][kind].push_back(int2{sidx, it});
+  const int uidx = (int)pl.upd.size();
+  pl.upd.push_back(s);
+  for (int b = 0; b < s.ntiles; ++b) pl.ublocks.push_back(int2{uidx, b});
 }
 
 // Descriptor array for a group, uploaded through the pinned stage into the device
@@ -337,6 +328,12 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   if (!st) st = c->stream;
   int64_t nsys_total = 0;
   for (size_t q = 0; q < asms.size(); ++q) nsys_total += Rs[q];
+  // blocks of 64 targets fill the device once there are at least as many as CUs;
+  // otherwise use blocks of 16 targets (4x more blocks)
+  int64_t blocks64 = 0;
+  for (size_t q = 0; q < asms.size(); ++q)
+    if (!wants_resident(asms[q], nsys_total)) blocks64 += Rs[q] * ((asms[q]->n + 63) / 64);
+  const int kind_new = blocks64 >= c->n_cu ? 0 : 1;
   Plan pl;
   std::vector<std::pair<mh_asm*, std::pair<int, int>>> fin;  // asm -> range in all-sys list
   std::vector<SysDesc> all;
@@ -345,7 +342,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     if (a->p.precision == MH_BF16X3_WM) return MH_EINVAL;  // handled by the matrix path
     const bool res = wants_resident(a, nsys_total);
     if (o.init) {
-      int e = prepare_run(a, Rs[q], seeds[q], res);
+      int e = prepare_run(a, Rs[q], seeds[q], res, kind_new);
       if (e) return e;
     }
     const bool fp64 = a->p.precision == MH_FP64;
@@ -359,26 +356,27 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
         (fp64 ? pl.res64 : pl.res32).push_back(s);
         int& nm = fp64 ? pl.nmax_res64 : pl.nmax_res32;
         nm = std::max(nm, (int)a->n);
-      } else if (fp64) {
-        add_tiled(pl, pl.til64, pl.tasks64, pl.part64, s);
       } else {
-        add_tiled(pl, pl.til32, pl.tasks32, pl.part32, s);
+        add_tiled(pl, fp64 ? 1 : 0, a->tile_kind, s);
       }
       pl.kmax = std::max<int64_t>(pl.kmax, s.total_steps);
       pl.nmax_all = std::max(pl.nmax_all, (int)a->n);
     }
     fin.push_back({a, {first, (int)all.size()}});
   }
-  // upload descriptors and tasks
+  // upload descriptors and tile lists
   size_t bytes = 0;
   auto add = [&](size_t b) { bytes = ((bytes + 255) & ~(size_t)255) + b; };
   add(sizeof(SysDesc) * all.size());
   add(sizeof(SysDesc) * pl.res64.size());
   add(sizeof(SysDesc) * pl.res32.size());
-  add(sizeof(SysDesc) * pl.til64.size());
-  add(sizeof(SysDesc) * pl.til32.size());
-  add(sizeof(Task) * pl.tasks64.size());
-  add(sizeof(Task) * pl.tasks32.size());
+  for (int f = 0; f < 2; ++f)
+    for (int kd = 0; kd < 2; ++kd) {
+      add(sizeof(SysDesc) * pl.til[f][kd].size());
+      add(sizeof(int2) * pl.tiles[f][kd].size());
+    }
+  add(sizeof(SysDesc) * pl.upd.size());
+  add(sizeof(int2) * pl.ublocks.size());
   bytes += 256;
   if (hipStreamSynchronize(st) != hipSuccess) return MH_EDEVICE;  // stage reuse
   int e;
@@ -388,16 +386,15 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   SysDesc* d_all = stage_upload(c, all, off, st);
   SysDesc* d_res64 = stage_upload(c, pl.res64, off, st);
   SysDesc* d_res32 = stage_upload(c, pl.res32, off, st);
-  SysDesc* d_til64 = stage_upload(c, pl.til64, off, st);
-  SysDesc* d_til32 = stage_upload(c, pl.til32, off, st);
-  Task* d_t64 = stage_upload(c, pl.tasks64, off, st);
-  Task* d_t32 = stage_upload(c, pl.tasks32, off, st);
-  if ((e = c->d_part.ensure(sizeof(D4) * (pl.part64 + 1) + sizeof(F4) * (pl.part32 + 1)))) return e;
-  if ((e = c->d_ctr.ensure(sizeof(unsigned) * (pl.nctr + 1)))) return e;
-  D4* part64 = c->d_part.as<D4>();
-  F4* part32 = reinterpret_cast<F4*>(part64 + pl.part64 + 1);
-  if (hipMemsetAsync(c->d_ctr.p, 0, sizeof(unsigned) * (pl.nctr + 1), st) != hipSuccess)
-    return MH_EDEVICE;
+  SysDesc* d_til[2][2];
+  int2* d_tiles[2][2];
+  for (int f = 0; f < 2; ++f)
+    for (int kd = 0; kd < 2; ++kd) {
+      d_til[f][kd] = stage_upload(c, pl.til[f][kd], off, st);
+      d_tiles[f][kd] = stage_upload(c, pl.tiles[f][kd], off, st);
+    }
+  SysDesc* d_upd = stage_upload(c, pl.upd, off, st);
+  int2* d_ublocks = stage_upload(c, pl.ublocks, off, st);
   if (o.init) {
     if (launch_init(d_all, (int)all.size(), pl.nmax_all, st) != hipSuccess) return MH_EDEVICE;
   } else {
@@ -408,7 +405,9 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   const int64_t k0 = o.k0;
   const int64_t k1 = o.k1 < 0 ? pl.kmax : std::min<int64_t>(o.k1, pl.kmax);
   const bool any_res = !pl.res64.empty() || !pl.res32.empty();
-  const bool any_til = !pl.tasks64.empty() || !pl.tasks32.empty();
+  bool any_til = false;
+  for (int f = 0; f < 2; ++f)
+    for (int kd = 0; kd < 2; ++kd) any_til = any_til || !pl.tiles[f][kd].empty();
   int tq = any_res && k1 > k0 ? timing_begin(c, st, 1) : -1;
   if (launch_resident(true, d_res64, (int)pl.res64.size(), k0, k1, pl.nmax_res64, st) != hipSuccess)
     return MH_EDEVICE;
@@ -418,16 +417,17 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   timing_end(c, st, tq);
   for (int64_t k = k0; k < k1 && any_til; ++k) {
     tq = timing_begin(c, st, 0);
-    if (launch_tiled(true, d_til64, d_t64, (int)pl.tasks64.size(), part64, c->d_ctr.as<unsigned>(),
-                     k, st) != hipSuccess)
-      return MH_EDEVICE;
-    if (launch_tiled(false, d_til32, d_t32, (int)pl.tasks32.size(), part32,
-                     c->d_ctr.as<unsigned>(), k, st) != hipSuccess)
+    for (int f = 0; f < 2; ++f)
+      for (int kd = 0; kd < 2; ++kd)
+        if (launch_field(f == 1, kd, d_til[f][kd], d_tiles[f][kd], (int)pl.tiles[f][kd].size(), k,
+                         st) != hipSuccess)
+          return MH_EDEVICE;
+    timing_end(c, st, tq);
+    tq = timing_begin(c, st, 3);
+    if (launch_update(d_upd, d_ublocks, (int)pl.ublocks.size(), k, st) != hipSuccess)
       return MH_EDEVICE;
     timing_end(c, st, tq);
   }
-  (void)d_til64;
-  (void)d_til32;
   if (o.finalize) {
     if (launch_finalize(d_all, (int)all.size(), st) != hipSuccess) return MH_EDEVICE;
     for (auto& f : fin) {
@@ -479,8 +479,6 @@ int mh_ctx_get_timing(mh_ctx* c, int32_t kind, double* total_ms, int64_t* launch
   }
   *total_ms = tot;
   *launches = cnt;
-  c->ev_used = 0;
-  c->ev_kind.clear();
   return MH_OK;
 }
 
@@ -590,7 +588,7 @@ int mh_destroy_assembly(mh_asm* a) {
     (void)hipEventDestroy(a->done);
   }
   DevBuf* bufs[] = {&a->pos64, &a->pos32, &a->axes, &a->m64, &a->m32, &a->area, &a->recpart,
-                    &a->rec, &a->sys_area, &a->stats, &a->diag, &a->tmp};
+                    &a->rec, &a->sys_area, &a->stats, &a->diag, &a->tmp, &a->field};
   for (auto* b : bufs) b->release();
   delete a;
   return MH_OK;
