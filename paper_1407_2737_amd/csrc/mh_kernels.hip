@@ -57,16 +57,17 @@ __device__ __forceinline__ F4* mom_of<float>(const SysDesc& s) {
 // Eq. 1 term of source j on target i in reduced units (positions / d): accumulates
 // (3 (m.r) r / r^2 - m) / r^3 with r = p_j - p_i; a coincident pair (j == i)
 // contributes nothing.
-template <typename T, typename P4, typename M4>
+template <typename T, bool kGuard = true, typename P4, typename M4>
 __device__ __forceinline__ void dip_pair(T xi, T yi, T zi, const P4& pj, const M4& mj, T& bx,
                                          T& by, T& bz) {
   const T dx = (T)pj.x - xi, dy = (T)pj.y - yi, dz = (T)pj.z - zi;
   const T r2 = dx * dx + dy * dy + dz * dz;
   T inv;
   if constexpr (sizeof(T) == 4)
-    inv = r2 > (T)0 ? rsqrtf(r2) : (T)0;
+    inv = rsqrtf(r2);
   else
-    inv = r2 > (T)0 ? (T)1 / sqrt(r2) : (T)0;
+    inv = (T)1 / sqrt(r2);
+  if constexpr (kGuard) inv = r2 > (T)0 ? inv : (T)0;
   const T inv2 = inv * inv;
   const T inv3 = inv2 * inv;
   const T md = (T)mj.x * dx + (T)mj.y * dy + (T)mj.z * dz;
@@ -218,7 +219,9 @@ __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ sy
 // ---------------------------------------------------------------------------
 template <typename T, int TI>
 __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ systems,
-                                                const int2* __restrict__ tiles, int64_t k) {
+                                                const int2* __restrict__ tiles,
+                                                const int64_t* __restrict__ kbase, int64_t koff) {
+  const int64_t k = (kbase ? *kbase : 0) + koff;
   using P4 = typename V4<T>::type;
   constexpr int L = 64 / TI;      // streams per wave
   constexpr int Q = 16 * L;       // streams per block
@@ -260,8 +263,15 @@ __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ syst
       }
       __syncthreads();
       const int ce = (cn + Q - 1) / Q * Q;  // streams stay in lockstep over padded entries
+      // only the chunk holding this block's targets can contain j == i
+      const bool self = (tl.y * TI < c0 + cn) && (tl.y * TI + TI > c0);
+      if (self) {
 #pragma unroll 4
-      for (int e = q; e < ce; e += Q) dip_pair<T>(xi, yi, zi, spos[e], smom[e], bx, by, bz);
+        for (int e = q; e < ce; e += Q) dip_pair<T, true>(xi, yi, zi, spos[e], smom[e], bx, by, bz);
+      } else {
+#pragma unroll 4
+        for (int e = q; e < ce; e += Q) dip_pair<T, false>(xi, yi, zi, spos[e], smom[e], bx, by, bz);
+      }
     }
   }
   red[0][q][il] = bx;
@@ -285,7 +295,9 @@ __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ syst
 }
 
 __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ systems,
-                                                const int2* __restrict__ blocks, int64_t k) {
+                                                const int2* __restrict__ blocks,
+                                                const int64_t* __restrict__ kbase, int64_t koff) {
+  const int64_t k = (kbase ? *kbase : 0) + koff;
   __shared__ double red[4];
   const int2 bl = blocks[blockIdx.x];
   const SysDesc& s = systems[bl.x];
@@ -457,27 +469,42 @@ hipError_t set_resident_lds_limit() {
 int tile_width(int kind) { return kind == 0 ? 64 : 16; }
 
 // kind 0: 64 targets per field block, kind 1: 16 targets per field block
+// The step index is *kbase + koff (kbase may be null): a captured graph of G steps
+// reads a device-side base that its last node advances by G.
 hipError_t launch_field(bool fp64, int kind, const SysDesc* d_sys, const int2* d_tiles, int ntiles,
-                        int64_t k, hipStream_t st) {
+                        const int64_t* kbase, int64_t koff, hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
   if (fp64) {
     if (kind == 0)
-      hipLaunchKernelGGL((k_field<double, 64>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, k);
+      hipLaunchKernelGGL((k_field<double, 64>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
+                         kbase, koff);
     else
-      hipLaunchKernelGGL((k_field<double, 16>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, k);
+      hipLaunchKernelGGL((k_field<double, 16>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
+                         kbase, koff);
   } else {
     if (kind == 0)
-      hipLaunchKernelGGL((k_field<float, 64>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, k);
+      hipLaunchKernelGGL((k_field<float, 64>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
+                         kbase, koff);
     else
-      hipLaunchKernelGGL((k_field<float, 16>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, k);
+      hipLaunchKernelGGL((k_field<float, 16>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
+                         kbase, koff);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks, int64_t k,
-                         hipStream_t st) {
+hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks,
+                         const int64_t* kbase, int64_t koff, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_update, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, k);
+  hipLaunchKernelGGL(k_update, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase, koff);
+  return hipGetLastError();
+}
+
+__global__ void k_set_step(int64_t* kbase, int64_t v, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *kbase = add ? *kbase + v : v;
+}
+
+hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, st, kbase, v, add ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -22,9 +22,10 @@ size_t resident_lds_bytes(bool fp64, int nmax);
 hipError_t set_resident_lds_limit();
 int tile_width(int kind);
 hipError_t launch_field(bool fp64, int kind, const SysDesc* d_sys, const int2* d_tiles, int ntiles,
-                        int64_t k, hipStream_t st);
-hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks, int64_t k,
-                         hipStream_t st);
+                        const int64_t* kbase, int64_t koff, hipStream_t st);
+hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks,
+                         const int64_t* kbase, int64_t koff, hipStream_t st);
+hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st);
 hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st);
 hipError_t launch_init(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st);
 hipError_t launch_sync32(const SysDesc* d_sys, int nsys, int nmax, int b, hipStream_t st);
@@ -93,13 +94,18 @@ struct mh_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   int n_cu = 256;
-  DevBuf d_sys, d_tasks, d_part, d_ctr;
+  DevBuf d_sys;
   PinBuf h_stage;
   // optional per-launch timing of the step kernels (event pairs around each launch)
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  std::vector<int> ev_kind;  // 0: tiled step, 1: resident run, 2: matrix step
+  std::vector<int> ev_kind;  // 0: tiled field, 1: resident run, 2: matrix step, 3: update
+  // captured graph of G tiled steps, reused while the launch plan is unchanged
+  DevBuf d_kbase;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gkey;
+  int use_graphs = 1;
 };
 
 struct mh_asm {
@@ -415,19 +421,65 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       hipSuccess)
     return MH_EDEVICE;
   timing_end(c, st, tq);
-  for (int64_t k = k0; k < k1 && any_til; ++k) {
-    tq = timing_begin(c, st, 0);
+  // one tiled step: dipolar fields, then the per-particle update
+  auto step = [&](const int64_t* kb, int64_t koff) -> int {
+    int t0 = timing_begin(c, st, 0);
     for (int f = 0; f < 2; ++f)
       for (int kd = 0; kd < 2; ++kd)
-        if (launch_field(f == 1, kd, d_til[f][kd], d_tiles[f][kd], (int)pl.tiles[f][kd].size(), k,
-                         st) != hipSuccess)
+        if (launch_field(f == 1, kd, d_til[f][kd], d_tiles[f][kd], (int)pl.tiles[f][kd].size(), kb,
+                         koff, st) != hipSuccess)
           return MH_EDEVICE;
-    timing_end(c, st, tq);
-    tq = timing_begin(c, st, 3);
-    if (launch_update(d_upd, d_ublocks, (int)pl.ublocks.size(), k, st) != hipSuccess)
+    timing_end(c, st, t0);
+    t0 = timing_begin(c, st, 3);
+    if (launch_update(d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st) != hipSuccess)
       return MH_EDEVICE;
-    timing_end(c, st, tq);
+    timing_end(c, st, t0);
+    return MH_OK;
+  };
+  int64_t k = k0;
+  constexpr int64_t G = 50;
+  if (any_til && c->use_graphs && !c->timing && k1 - k0 >= 2 * G) {
+    if ((e = c->d_kbase.ensure(sizeof(int64_t)))) return e;
+    int64_t* kb = c->d_kbase.as<int64_t>();
+    // the captured kernels read the plan from d_sys at fixed offsets: reuse the graph
+    // while the uploaded plan has the same layout
+    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)c->d_sys.p, (uint64_t)off, (uint64_t)G};
+    for (int f = 0; f < 2; ++f)
+      for (int kd = 0; kd < 2; ++kd) {
+        key.push_back((uint64_t)(uintptr_t)d_til[f][kd]);
+        key.push_back(pl.tiles[f][kd].size());
+      }
+    key.push_back((uint64_t)(uintptr_t)d_upd);
+    key.push_back(pl.ublocks.size());
+    if (!c->gexec || key != c->gkey) {
+      if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return MH_EDEVICE;
+      int rc = MH_OK;
+      for (int64_t j = 0; j < G && rc == MH_OK; ++j) rc = step(kb, j);
+      if (rc == MH_OK && launch_set_step(kb, G, true, st) != hipSuccess) rc = MH_EDEVICE;
+      if (hipStreamEndCapture(st, &g) != hipSuccess || rc != MH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return MH_EDEVICE;
+      }
+      const hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        c->gexec = nullptr;
+        return MH_EDEVICE;
+      }
+      c->gkey = key;
+    }
+    if (launch_set_step(kb, k0, false, st) != hipSuccess) return MH_EDEVICE;
+    for (; k + G <= k1; k += G)
+      if (hipGraphLaunch(c->gexec, st) != hipSuccess) return MH_EDEVICE;
   }
+  for (; k < k1 && any_til; ++k)
+    if ((e = step(nullptr, k))) return e;
   if (o.finalize) {
     if (launch_finalize(d_all, (int)all.size(), st) != hipSuccess) return MH_EDEVICE;
     for (auto& f : fin) {
@@ -523,10 +575,9 @@ int mh_ctx_destroy(mh_ctx* c) {
   if (!c) return MH_EINVAL;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->d_kbase.release();
   c->d_sys.release();
-  c->d_tasks.release();
-  c->d_part.release();
-  c->d_ctr.release();
   c->h_stage.release();
   (void)hipStreamDestroy(c->stream);
   delete c;
