@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c4plain"])
+    ap.add_argument("--replicas", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path is a single-device build; run with --gpus 1",
@@ -63,6 +65,9 @@ def main():
     import numpy as np
     import paper_1407_2737_amd as mh
     from paper_1407_2737_amd import workloads as W
+
+    if args.workload != "c2":
+        return bench_c4(args, mh, W)
 
     amps = (0.010, 0.020, 0.040)
     work = [W.config2(mu0Hmax=h, n_periods=args.periods) for h in amps]
@@ -128,6 +133,66 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(work)
+    print(json.dumps(line), flush=True)
+
+
+def bench_c4(args, mh, W):
+    """Replica-batched form: N=4096 in a 200 nm lysosome at phi=10 %, one axis set per
+    replica, R replicas on independent Philox streams; W.M on MFMA (c4) or the plain
+    FP32 N-body kernels on the same replicas (c4plain)."""
+    R = args.replicas
+    a4 = W.config4(n_axes_sets=R)
+    a4.mat.n_periods = args.periods
+    a4.mat.n_discard = min(a4.mat.n_discard, args.periods - 1)
+    prec = mh.BF16X3_WM if args.workload == "c4" else mh.FP32_FIELD
+    ctx = mh.Context(0)
+    asm = mh.Assembly(ctx, a4.pos, a4.axes, mh.params_from_material(a4.mat, prec), n_axes_sets=R)
+    steps_per_run = a4.mat.steps_per_period * a4.mat.n_periods
+
+    def one_run():
+        asm.run(R, seed=a4.seed)
+        asm.sync()
+        return asm.sar()
+
+    for _ in range(args.warmup):
+        one_run()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = one_run()
+    t1 = time.perf_counter()
+    ctx.set_timing(True)
+    one_run()
+    kind = 2 if args.workload == "c4" else 0
+    ms_k, launches = ctx.get_timing(kind)
+    ms_u, lu = ctx.get_timing(4 if args.workload == "c4" else 3)
+    ctx.set_timing(False)
+    wall = t1 - t0
+    n = a4.n
+    value = n * R * steps_per_run * args.steps / wall
+    avg = ms_k / 1e3 / max(launches, 1)
+    if args.workload == "c4":
+        alg = 2.0 * (3 * n) ** 2 * R          # one W.M product per step
+        roof = {"bound": "mfma", "achieved": alg / avg / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                "frac": alg / avg / 2.5e15, "traffic": None, "kernel": "k_wm_gemm",
+                "avg_launch_us": avg * 1e6, "launches": launches,
+                "mfma_utilisation_executed": 3 * alg / avg / 2.5e15,
+                "update_kernel_avg_us": ms_u * 1e3 / max(lu, 1)}
+    else:
+        alg = FLOPS_PER_PAIR * n * (n - 1) * R
+        roof = {"bound": "alu", "achieved": alg / avg / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": alg / avg / PEAK_FP32_VECTOR, "traffic": None,
+                "kernel": "k_field<float>", "avg_launch_us": avg * 1e6, "launches": launches,
+                "update_kernel_avg_us": ms_u * 1e3 / max(lu, 1)}
+    line = {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "bf16x3 mfma / f64 barrier" if args.workload == "c4" else "f32 field / f64 barrier",
+            "data": "synthetic",
+            "config": {"workload": f"config4 ({args.workload}): N={n}, R={R} replicas, 200 nm, "
+                                   f"phi=10%, d={a4.mat.d * 1e9:.2f} nm, 20 mT, {args.periods} periods",
+                       "sar_W_per_g": res["sar"] / 1e3, "sar_se_W_per_g": res["sar_se"] / 1e3},
+            "roofline": roof}
     print(json.dumps(line), flush=True)
 
 

@@ -40,9 +40,72 @@ struct SysDesc {
   int32_t pad_;
 };
 
+// Operands of the interaction-matrix product (see mh_wm.hip).
+struct WMArgs {
+  const __bf16* whi;
+  const __bf16* wlo;
+  __bf16* mhi;     // M^T hi: Rp x Kp
+  __bf16* mlo;     // M^T lo
+  float* bt;       // B^T: Rp x Mp (reduced dipolar sums)
+  int Mp, Kp, Rp;
+  int n_rtiles;    // Mp / WM_BN
+  int n_ctiles;    // Rp / WM_BM
+};
+
 __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {
   if (s.static_field) return s.Bmax;
   return s.Bmax * cos(2.0 * kPi * (double)k / (double)s.S);
+}
+
+// Steps iii-vii for particle i of system s with the reduced dipolar sum (ax, ay, az)
+// from the moments in buffer cur; writes buffer cur^1, accumulates the area, and
+// returns the new m_x.
+__device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur, double ax, double ay,
+                              double az) {
+  if (s.field_only) {
+    double* d = s.diag + (int64_t)i * 8;
+    d[0] = s.Bscale * ax;
+    d[1] = s.Bscale * ay;
+    d[2] = s.Bscale * az;
+    return 0.0;
+  }
+  const double Bext = applied_field(s, k);
+  const double Bx = Bext + s.Bscale * ax, By = s.Bscale * ay, Bz = s.Bscale * az;
+  const D4 mo = s.m64[(int64_t)cur * s.stride + i];
+  const D4 nn = s.axes[i];
+  const NPResult r =
+      np_update(s.np, Bx, By, Bz, nn.x, nn.y, nn.z, mo.x, mo.y, mo.z, s.seed, s.stream, i, k);
+  const int nxt = cur ^ 1;
+  D4 mn;
+  mn.x = r.mx;
+  mn.y = r.my;
+  mn.z = r.mz;
+  mn.w = 0.0;
+  s.m64[(int64_t)nxt * s.stride + i] = mn;
+  F4 mf;
+  mf.x = (float)r.mx;
+  mf.y = (float)r.my;
+  mf.z = (float)r.mz;
+  mf.w = 0.f;
+  s.m32[(int64_t)nxt * s.stride + i] = mf;
+  if (k >= s.kept0) {
+    double sum = s.area[i], comp = s.area[s.n + i];
+    neumaier_add(sum, comp, s.Ms * Bext * (r.mx - mo.x));
+    s.area[i] = sum;
+    s.area[s.n + i] = comp;
+  }
+  if (s.diag) {
+    double* d = s.diag + (int64_t)i * 8;
+    d[0] = Bx;
+    d[1] = By;
+    d[2] = Bz;
+    d[3] = r.P;
+    d[4] = (double)r.jump;
+    d[5] = (double)r.two;
+    d[6] = 0.0;
+    d[7] = 0.0;
+  }
+  return r.mx;
 }
 
 }  // namespace mh

@@ -26,6 +26,16 @@ hipError_t launch_field(bool fp64, int kind, const SysDesc* d_sys, const int2* d
 hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks,
                          const int64_t* kbase, int64_t koff, hipStream_t st);
 hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st);
+int wm_tile_rows();
+int wm_tile_reps();
+int wm_tile_k();
+hipError_t launch_wm_build(const D4* pos, int n, __bf16* whi, __bf16* wlo, int Mp, int Kp,
+                           hipStream_t st);
+hipError_t launch_wm_gemm(const WMArgs& g, hipStream_t st);
+hipError_t launch_wm_update(const SysDesc* d_sys, int R, int n, const WMArgs& g,
+                            const int64_t* kbase, int64_t koff, hipStream_t st);
+hipError_t launch_wm_pack(const SysDesc* d_sys, int R, int n, const WMArgs& g, int b,
+                          hipStream_t st);
 hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st);
 hipError_t launch_init(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st);
 hipError_t launch_sync32(const SysDesc* d_sys, int nsys, int nmax, int b, hipStream_t st);
@@ -123,6 +133,10 @@ struct mh_asm {
   int resident = 0;
   int tile_kind = 0;  // 0: 64 targets per block, 1: 16
   DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp, field;
+  // interaction-matrix form: W hi/lo (Mp x Kp), M^T hi/lo (Rp x Kp), B^T (Rp x Mp)
+  DevBuf whi, wlo, mhi, mlo, bt;
+  int Mp = 0, Kp = 0, Rp = 0;
+  bool w_built = false;
   int state_parity = 0;  // the current moments live in buffer state_parity
   hipEvent_t done = nullptr;
   // host copy of the per-run system descriptors (for diagnostics re-runs)
@@ -215,7 +229,35 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   if ((e = a->rec.ensure(sizeof(double) * R * rows + 8))) return e;
   if ((e = a->sys_area.ensure(sizeof(double) * R))) return e;
   if ((e = a->stats.ensure(sizeof(double) * 4))) return e;
-  if (!resident && (e = a->field.ensure(sizeof(D4) * R * n))) return e;
+  const bool wm = a->p.precision == MH_BF16X3_WM;
+  if (!resident && !wm && (e = a->field.ensure(sizeof(D4) * R * n))) return e;
+  if (wm) {
+    if (!a->w_built) {
+      const int64_t rows = 3 * n;
+      const int64_t rq = 8 * wm_tile_rows();  // whole row tiles, a multiple of 8 for the XCD map
+      a->Mp = (int)((rows + rq - 1) / rq * rq);
+      a->Kp = (int)((rows + wm_tile_k() - 1) / wm_tile_k() * wm_tile_k());
+      const size_t wb = sizeof(__bf16) * (size_t)a->Mp * a->Kp;
+      if ((e = a->whi.ensure(wb)) || (e = a->wlo.ensure(wb))) return e;
+      if (launch_wm_build(a->pos64.as<D4>(), (int)n, a->whi.as<__bf16>(), a->wlo.as<__bf16>(),
+                          a->Mp, a->Kp, a->ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(a->ctx->stream) != hipSuccess)
+        return MH_EDEVICE;
+      a->w_built = true;
+    }
+    const int rt = wm_tile_reps();
+    const int Rp = (int)((R + rt - 1) / rt * rt);
+    const size_t mb = sizeof(__bf16) * (size_t)Rp * a->Kp;
+    if (Rp != a->Rp || !a->mhi.p) {
+      a->mhi.release();
+      a->mlo.release();
+      if ((e = a->mhi.ensure(mb)) || (e = a->mlo.ensure(mb))) return e;
+      if (hipMemset(a->mhi.p, 0, mb) != hipSuccess || hipMemset(a->mlo.p, 0, mb) != hipSuccess)
+        return MH_EDEVICE;
+      a->Rp = Rp;
+    }
+    if ((e = a->bt.ensure(sizeof(float) * (size_t)Rp * a->Mp))) return e;
+  }
   a->R = R;
   a->seed = seed;
   return MH_OK;
@@ -262,9 +304,31 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   return s;
 }
 
+WMArgs wm_args(const mh_asm* a) {
+  WMArgs g{};
+  g.whi = a->whi.as<__bf16>();
+  g.wlo = a->wlo.as<__bf16>();
+  g.mhi = a->mhi.as<__bf16>();
+  g.mlo = a->mlo.as<__bf16>();
+  g.bt = a->bt.as<float>();
+  g.Mp = a->Mp;
+  g.Kp = a->Kp;
+  g.Rp = a->Rp;
+  g.n_rtiles = a->Mp / wm_tile_rows();
+  g.n_ctiles = a->Rp / wm_tile_reps();
+  return g;
+}
+
+struct WMItem {
+  mh_asm* a;
+  int first;  // index of replica 0 in the all-systems list
+  WMArgs g;
+};
+
 struct Plan {
   std::vector<SysDesc> res64, res32, til[2][2];  // til[fp64][kind]
   std::vector<int2> tiles[2][2];
+  std::vector<WMItem> wm;
   std::vector<SysDesc> upd;   // all tiled systems
   std::vector<int2> ublocks;  // (system in upd, block of 256 particles)
   int nmax_res64 = 0, nmax_res32 = 0;
@@ -345,7 +409,6 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   std::vector<SysDesc> all;
   for (size_t q = 0; q < asms.size(); ++q) {
     mh_asm* a = asms[q];
-    if (a->p.precision == MH_BF16X3_WM) return MH_EINVAL;  // handled by the matrix path
     const bool res = wants_resident(a, nsys_total);
     if (o.init) {
       int e = prepare_run(a, Rs[q], seeds[q], res, kind_new);
@@ -358,7 +421,9 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       s.field_only = o.field_only ? 1 : 0;
       if (o.diag) s.diag = o.diag + r * a->n * 8;
       all.push_back(s);
-      if (a->resident) {
+      if (a->p.precision == MH_BF16X3_WM) {
+        // handled by the matrix path below
+      } else if (a->resident) {
         (fp64 ? pl.res64 : pl.res32).push_back(s);
         int& nm = fp64 ? pl.nmax_res64 : pl.nmax_res32;
         nm = std::max(nm, (int)a->n);
@@ -369,6 +434,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       pl.nmax_all = std::max(pl.nmax_all, (int)a->n);
     }
     fin.push_back({a, {first, (int)all.size()}});
+    if (a->p.precision == MH_BF16X3_WM) pl.wm.push_back(WMItem{a, first, wm_args(a)});
   }
   // upload descriptors and tile lists
   size_t bytes = 0;
@@ -408,10 +474,14 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     if (launch_sync32(d_all, (int)all.size(), pl.nmax_all, (int)(o.k0 & 1), st) != hipSuccess)
       return MH_EDEVICE;
   }
+  for (auto& it : pl.wm)
+    if (launch_wm_pack(d_all + it.first, (int)it.a->R, (int)it.a->n, it.g, (int)(o.k0 & 1), st) !=
+        hipSuccess)
+      return MH_EDEVICE;
   const int64_t k0 = o.k0;
   const int64_t k1 = o.k1 < 0 ? pl.kmax : std::min<int64_t>(o.k1, pl.kmax);
   const bool any_res = !pl.res64.empty() || !pl.res32.empty();
-  bool any_til = false;
+  bool any_til = !pl.wm.empty();
   for (int f = 0; f < 2; ++f)
     for (int kd = 0; kd < 2; ++kd) any_til = any_til || !pl.tiles[f][kd].empty();
   int tq = any_res && k1 > k0 ? timing_begin(c, st, 1) : -1;
@@ -434,6 +504,16 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     if (launch_update(d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st) != hipSuccess)
       return MH_EDEVICE;
     timing_end(c, st, t0);
+    for (auto& it : pl.wm) {
+      t0 = timing_begin(c, st, 2);
+      if (launch_wm_gemm(it.g, st) != hipSuccess) return MH_EDEVICE;
+      timing_end(c, st, t0);
+      t0 = timing_begin(c, st, 4);
+      if (launch_wm_update(d_all + it.first, (int)it.a->R, (int)it.a->n, it.g, kb, koff, st) !=
+          hipSuccess)
+        return MH_EDEVICE;
+      timing_end(c, st, t0);
+    }
     return MH_OK;
   };
   int64_t k = k0;
@@ -451,6 +531,12 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       }
     key.push_back((uint64_t)(uintptr_t)d_upd);
     key.push_back(pl.ublocks.size());
+    for (auto& it : pl.wm) {
+      const uint64_t* gw = reinterpret_cast<const uint64_t*>(&it.g);
+      for (size_t q = 0; q < sizeof(WMArgs) / 8; ++q) key.push_back(gw[q]);
+      key.push_back((uint64_t)it.first);
+      key.push_back((uint64_t)it.a->R);
+    }
     if (!c->gexec || key != c->gkey) {
       if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -639,7 +725,8 @@ int mh_destroy_assembly(mh_asm* a) {
     (void)hipEventDestroy(a->done);
   }
   DevBuf* bufs[] = {&a->pos64, &a->pos32, &a->axes, &a->m64, &a->m32, &a->area, &a->recpart,
-                    &a->rec, &a->sys_area, &a->stats, &a->diag, &a->tmp, &a->field};
+                    &a->rec, &a->sys_area, &a->stats, &a->diag, &a->tmp, &a->field,
+                    &a->whi, &a->wlo, &a->mhi, &a->mlo, &a->bt};
   for (auto* b : bufs) b->release();
   delete a;
   return MH_OK;
@@ -755,7 +842,6 @@ int mh_get_moments(mh_asm* a, int64_t replica, double* m) {
 int mh_debug_steps(mh_asm* a, int64_t n_replicas, uint64_t seed, int64_t k0, int64_t k1,
                    const double* m_in, double* diag) {
   if (!a || n_replicas < 1 || k0 < 0 || k1 < k0 || k1 > total_steps(a->p)) return MH_EINVAL;
-  if (a->p.precision == MH_BF16X3_WM) return MH_EINVAL;
   if (set_dev(a->ctx)) return MH_EDEVICE;
   std::vector<mh_asm*> v{a};
   std::vector<int64_t> R{n_replicas};
@@ -806,7 +892,6 @@ int mh_debug_steps(mh_asm* a, int64_t n_replicas, uint64_t seed, int64_t k0, int
 
 int mh_debug_field(mh_asm* a, const double* m, double* B_out) {
   if (!a || !m || !B_out) return MH_EINVAL;
-  if (a->p.precision == MH_BF16X3_WM) return MH_EINVAL;
   if (set_dev(a->ctx)) return MH_EDEVICE;
   const int64_t n = a->n;
   std::vector<mh_asm*> v{a};
