@@ -54,7 +54,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c4plain"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c4plain"])
+    ap.add_argument("--assemblies", type=int, default=256)
     ap.add_argument("--replicas", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -66,6 +67,8 @@ def main():
     import paper_1407_2737_amd as mh
     from paper_1407_2737_amd import workloads as W
 
+    if args.workload == "c3":
+        return bench_c3(args, mh, W)
     if args.workload != "c2":
         return bench_c4(args, mh, W)
 
@@ -133,6 +136,56 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(work)
+    print(json.dumps(line), flush=True)
+
+
+def bench_c3(args, mh, W):
+    """Batched uneven assemblies: 256 lysosomes with R ~ U(100,250) nm, phi ~ U(1,20) %,
+    d ~ U(10,16) nm, K ~ U(0.8,2)e4, Hmax ~ U(5,40) mT, N in [200, 8000], one replica
+    each, FP32 field, run together."""
+    work = W.config3(count=args.assemblies, n_periods=args.periods)
+    ctx = mh.Context(0)
+    asms = [mh.Assembly(ctx, w.pos, w.axes, mh.params_from_material(w.mat, mh.FP32_FIELD))
+            for w in work]
+    seeds = [w.seed for w in work]
+    npsteps = sum(w.n * w.mat.steps_per_period * w.mat.n_periods for w in work)
+
+    def one_run():
+        mh.run_batch(asms, [1] * len(asms), seeds)
+        for a in asms:
+            a.sync()
+        return [a.sar()["sar"] for a in asms]
+
+    for _ in range(args.warmup):
+        one_run()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sars = one_run()
+    t1 = time.perf_counter()
+    ctx.set_timing(True)
+    one_run()
+    ms_k, launches = ctx.get_timing(0)
+    ms_u, lu = ctx.get_timing(3)
+    ms_r, lr = ctx.get_timing(1)
+    ctx.set_timing(False)
+    wall = t1 - t0
+    value = npsteps * args.steps / wall
+    pairs = sum(w.n * (w.n - 1) for w in work if w.n > 256)
+    avg = ms_k / 1e3 / max(launches, 1)
+    roof = {"bound": "alu", "achieved": FLOPS_PER_PAIR * pairs / avg / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
+            "frac": FLOPS_PER_PAIR * pairs / avg / PEAK_FP32_VECTOR, "traffic": None,
+            "kernel": "k_field<float>", "avg_launch_us": avg * 1e6, "launches": launches,
+            "update_kernel_avg_us": ms_u * 1e3 / max(lu, 1), "resident_ms": ms_r}
+    line = {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 field / f64 barrier", "data": "synthetic",
+            "config": {"workload": f"config3: {len(work)} uneven assemblies, N {min(w.n for w in work)}"
+                                   f"-{max(w.n for w in work)}, {args.periods} periods x 2000 steps",
+                       "n_particles_total": sum(w.n for w in work),
+                       "sar_W_per_g_median": float(sorted(sars)[len(sars) // 2]) / 1e3},
+            "roofline": roof}
     print(json.dumps(line), flush=True)
 
 

@@ -204,14 +204,20 @@ int check_overlap(int64_t n, const double* pos, double d) {
   return MH_OK;
 }
 
-bool wants_resident(const mh_asm* a, int64_t nsys_total) {
+// Launch form of an assembly, decided from its own size and replica count only, so
+// that its results do not depend on what else runs in the same batch.
+bool wants_resident(const mh_asm* a, int64_t R) {
   if (a->p.precision == MH_BF16X3_WM) return false;
   const bool fp64 = a->p.precision == MH_FP64;
-  const int64_t cap = fp64 ? 1024 : 2048;
-  if (a->n > cap) return false;
   if (a->n <= 256) return true;
-  // a single workgroup per system pays off once many systems fill the device
-  return nsys_total >= 4 * a->ctx->n_cu && a->n <= (fp64 ? 512 : 1024);
+  // a single workgroup per replica pays off once its replicas fill the device
+  return R >= 4 * a->ctx->n_cu && a->n <= (fp64 ? 512 : 1024);
+}
+
+// Field tile width: 64 targets per block once the assembly's own blocks fill the
+// device, else 16 (four times more blocks).
+int tile_kind_for(const mh_asm* a, int64_t R) {
+  return R * ((a->n + 63) / 64) >= a->ctx->n_cu ? 0 : 1;
 }
 
 // (Re)allocate a replica set and its per-run buffers.
@@ -396,22 +402,14 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     if (a->ctx != c) return MH_EINVAL;
   if (set_dev(c)) return MH_EDEVICE;
   if (!st) st = c->stream;
-  int64_t nsys_total = 0;
-  for (size_t q = 0; q < asms.size(); ++q) nsys_total += Rs[q];
-  // blocks of 64 targets fill the device once there are at least as many as CUs;
-  // otherwise use blocks of 16 targets (4x more blocks)
-  int64_t blocks64 = 0;
-  for (size_t q = 0; q < asms.size(); ++q)
-    if (!wants_resident(asms[q], nsys_total)) blocks64 += Rs[q] * ((asms[q]->n + 63) / 64);
-  const int kind_new = blocks64 >= c->n_cu ? 0 : 1;
+
   Plan pl;
   std::vector<std::pair<mh_asm*, std::pair<int, int>>> fin;  // asm -> range in all-sys list
   std::vector<SysDesc> all;
   for (size_t q = 0; q < asms.size(); ++q) {
     mh_asm* a = asms[q];
-    const bool res = wants_resident(a, nsys_total);
     if (o.init) {
-      int e = prepare_run(a, Rs[q], seeds[q], res, kind_new);
+      int e = prepare_run(a, Rs[q], seeds[q], wants_resident(a, Rs[q]), tile_kind_for(a, Rs[q]));
       if (e) return e;
     }
     const bool fp64 = a->p.precision == MH_FP64;

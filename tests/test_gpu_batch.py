@@ -1,0 +1,66 @@
+"""Batched uneven assemblies (one fused launch sequence for many assemblies of
+different sizes, materials, fields and protocols): every assembly's result must be
+bitwise the same as when it runs alone with the same replicas and seed, and an FP64
+member must still follow the oracle."""
+import numpy as np
+import pytest
+
+from oracle import kmc
+from paper_1407_2737_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _members(lib):
+    rng = np.random.default_rng(31)
+    out = []
+    specs = [(40, lib.FP64), (150, lib.FP32_FIELD), (300, lib.FP64), (700, lib.FP32_FIELD),
+             (1200, lib.FP32_FIELD), (2500, lib.FP32_FIELD), (90, lib.FP32_FIELD),
+             (600, lib.BF16X3_WM), (1000, lib.FP64)]
+    for q, (n, prec) in enumerate(specs):
+        phi = rng.uniform(0.02, 0.15)
+        d = rng.uniform(10e-9, 16e-9)
+        R = d / 2 * (n / phi) ** (1 / 3)
+        pos = W.place_random(n, R, d, 40 + q)
+        axes = W.axes_random_3d(n, 60 + q)
+        P = int(rng.integers(2, 4))
+        kw = dict(Ms=4e5, Keff=float(rng.uniform(0.8e4, 2e4)), d=d, T=300.0, tau0=1e-10,
+                  rho=5200.0, f=float(rng.uniform(1e5, 1e6)), mu0Hmax=float(rng.uniform(0.005, 0.04)),
+                  steps_per_period=int(rng.choice([60, 100, 140])), n_periods=P, n_discard=1)
+        out.append((pos, axes, kw, prec, int(rng.integers(1, 4)), 1000 + q))
+    return out
+
+
+def test_batch_equals_alone(lib):
+    ctx = lib.Context(0)
+    mem = _members(lib)
+    alone = []
+    for pos, axes, kw, prec, R, seed in mem:
+        a = lib.Assembly(ctx, pos, axes, lib.Params.make(prec, **kw))
+        a.run(R, seed)
+        a.sync()
+        alone.append((a.replica_areas().copy(), [a.moments(r).copy() for r in range(R)],
+                      a.loop(0, 0)[1].copy()))
+        a.close()
+    asms = [lib.Assembly(ctx, pos, axes, lib.Params.make(prec, **kw))
+            for pos, axes, kw, prec, R, seed in mem]
+    lib.run_batch(asms, [m[4] for m in mem], [m[5] for m in mem])
+    for q, a in enumerate(asms):
+        a.sync()
+        areas = a.replica_areas()
+        assert np.array_equal(areas, alone[q][0]), q
+        for r in range(mem[q][4]):
+            assert np.array_equal(a.moments(r), alone[q][1][r]), (q, r)
+        assert np.array_equal(a.loop(0, 0)[1], alone[q][2]), q
+    # the FP64 members follow the oracle
+    for q, (pos, axes, kw, prec, R, seed) in enumerate(mem):
+        if prec != lib.FP64 or len(pos) > 400:
+            continue
+        ref = kmc.simulate(pos, axes, kmc.Params(**kw), seed=seed, stream=0)
+        assert np.abs(asms[q].moments(0) - ref.m_final).max() < 1e-8
+        assert abs(asms[q].replica_areas()[0] - ref.area) < 1e-9 * max(1.0, abs(ref.area))
+    # a second batch on the same assemblies reuses the captured graph and repeats
+    lib.run_batch(asms, [m[4] for m in mem], [m[5] for m in mem])
+    for q, a in enumerate(asms):
+        a.sync()
+        assert np.array_equal(a.replica_areas(), alone[q][0]), q
