@@ -147,6 +147,49 @@ int mh_debug_sw(mh_ctx* ctx, int64_t n, const double* hx, const double* hy,
  * precision the assembly was created with. B_out: n x 3. */
 int mh_debug_field(mh_asm* a, const double* m, double* B_out);
 
+/* ---------------------------------------------------------------------------
+ * Continuous-batching server. A scheduler thread admits queued requests in arrival
+ * order while their device memory (state, and W for the matrix form) fits the budget,
+ * and advances every admitted request together, chunk by chunk, so requests that
+ * arrive while others run start as soon as memory frees up and share the launches.
+ * Each request runs rounds of up to 64 replicas (256 for the matrix form; replica r
+ * uses Philox stream r) until
+ * 2 SE <= max(target_rel_err |A|, 1e-3 * 2 Keff) with at least min_replicas, or
+ * max_replicas. A request's result is the same alone and in any mix.
+ * ------------------------------------------------------------------------- */
+typedef struct mh_server mh_server;
+
+typedef struct {
+  int64_t n;              /* particles */
+  const double* pos;      /* n x 3, m (copied at submit) */
+  const double* axes;     /* n_axes_sets x n x 3 (copied at submit) */
+  int64_t n_axes_sets;
+  mh_params params;
+  uint64_t seed;
+  double target_rel_err;  /* relative target for 2 SE of the area (e.g. 0.01) */
+  int64_t min_replicas, max_replicas;
+} mh_request;
+
+typedef struct {
+  double sar_Wkg, sar_se;   /* W/kg */
+  double area_Jm3, area_se; /* J/m^3 */
+  int64_t loops;            /* kept loops = replicas x kept periods */
+  int64_t replicas;
+  uint64_t submit_ns, start_ns, done_ns; /* steady-clock stamps: submit, admission, result */
+  int32_t status;           /* MH_OK or an error code */
+} mh_result;
+
+/* hbm_budget_bytes: device memory the server may hold for admitted requests. The
+ * server runs on a private context of ctx's device. */
+int mh_server_create(mh_ctx* ctx, size_t hbm_budget_bytes, mh_server** out);
+/* Copies the request; MH_EBUDGET if it can never fit the budget, MH_EOVERLAP/MH_EINVAL
+ * for invalid inputs. Thread-safe. */
+int mh_server_submit(mh_server* s, const mh_request* req, uint64_t* req_id);
+/* MH_ENOTREADY until the request finished; then fills *out. Thread-safe. */
+int mh_server_poll(mh_server* s, uint64_t req_id, mh_result* out);
+/* Stops after the admitted requests finish (queued ones are dropped) and frees all. */
+int mh_server_destroy(mh_server* s);
+
 /* Launch timing (diagnostics for roofline reports). When on, every step-kernel launch
  * is bracketed by a pair of HIP events on the stream it runs on. mh_ctx_get_timing
  * waits for the recorded launches of one kind (0: tiled dipolar-field kernel, 1: resident

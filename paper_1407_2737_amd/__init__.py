@@ -24,6 +24,7 @@ SYMBOLS = [
     "mh_run_loops", "mh_run_batch", "mh_sync", "mh_get_loop", "mh_get_sar",
     "mh_get_replica_areas", "mh_get_moments", "mh_debug_steps", "mh_debug_philox",
     "mh_debug_sw", "mh_debug_field", "mh_strerror", "mh_ctx_set_timing", "mh_ctx_get_timing",
+    "mh_server_create", "mh_server_submit", "mh_server_poll", "mh_server_destroy",
 ]
 
 
@@ -52,6 +53,20 @@ class Params(C.Structure):
             setattr(p, k, v)
         p.precision = precision
         return p
+
+
+class Request(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", C.POINTER(C.c_double)), ("axes", C.POINTER(C.c_double)),
+                ("n_axes_sets", C.c_int64), ("params", Params), ("seed", C.c_uint64),
+                ("target_rel_err", C.c_double), ("min_replicas", C.c_int64),
+                ("max_replicas", C.c_int64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("sar_Wkg", C.c_double), ("sar_se", C.c_double), ("area_Jm3", C.c_double),
+                ("area_se", C.c_double), ("loops", C.c_int64), ("replicas", C.c_int64),
+                ("submit_ns", C.c_uint64), ("start_ns", C.c_uint64), ("done_ns", C.c_uint64),
+                ("status", C.c_int32)]
 
 
 _L = None
@@ -84,6 +99,10 @@ def _lib():
             "mh_strerror": ([C.c_int], C.c_char_p),
             "mh_ctx_set_timing": ([vp, C.c_int], C.c_int),
             "mh_ctx_get_timing": ([vp, i32, dp, C.POINTER(i64)], C.c_int),
+            "mh_server_create": ([vp, C.c_size_t, C.POINTER(vp)], C.c_int),
+            "mh_server_submit": ([vp, C.POINTER(Request), C.POINTER(u64)], C.c_int),
+            "mh_server_poll": ([vp, u64, C.POINTER(Result)], C.c_int),
+            "mh_server_destroy": ([vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -227,6 +246,45 @@ class Assembly:
         out = np.empty((self.n, 3))
         _check(_lib().mh_debug_field(self._h, _dp(m), _dp(out)), "mh_debug_field")
         return out
+
+
+class Server:
+    """Continuous-batching server (mh_server_*)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int):
+        self._h = C.c_void_p()
+        _check(_lib().mh_server_create(ctx._h, hbm_budget_bytes, C.byref(self._h)),
+               "mh_server_create")
+
+    def submit(self, pos, axes, params: Params, seed: int, target_rel_err: float = 0.01,
+               min_replicas: int = 64, max_replicas: int = 8192, n_axes_sets: int = 1) -> int:
+        pos = _f64(pos)
+        axes = _f64(axes, (n_axes_sets * pos.shape[0], 3))
+        rq = Request(pos.shape[0], _dp(pos), _dp(axes), n_axes_sets, params, seed, target_rel_err,
+                     min_replicas, max_replicas)
+        rid = C.c_uint64()
+        _check(_lib().mh_server_submit(self._h, C.byref(rq), C.byref(rid)), "mh_server_submit")
+        return rid.value
+
+    def poll(self, rid: int):
+        """Result dict, or None while the request is not finished."""
+        res = Result()
+        rc = _lib().mh_server_poll(self._h, rid, C.byref(res))
+        if rc == ENOTREADY:
+            return None
+        _check(rc, "mh_server_poll")
+        return {f: getattr(res, f) for f, _ in Result._fields_}
+
+    def close(self):
+        if self._h:
+            _lib().mh_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def run_batch(assemblies, n_replicas, seeds, stream=None):

@@ -106,7 +106,11 @@ __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ sy
   const int tid = threadIdx.x;
   const P4* gpos = pos_of<T>(s);
   const P4* gmom = mom_of<T>(s);
-  const int cur0 = (int)(k0 & 1);
+  // local step range of this system within the launch's global range
+  const int64_t kl0 = k0 - s.k_origin > 0 ? k0 - s.k_origin : 0;
+  const int64_t kl1 = k1 - s.k_origin < (int64_t)s.total_steps ? k1 - s.k_origin : s.total_steps;
+  if (kl0 >= kl1) return;
+  const int cur0 = (int)(kl0 & 1);
   for (int j = tid; j < n; j += 256) {
     pos[j] = gpos[j];
     mom[(int64_t)cur0 * nmax + j] = gmom[(int64_t)cur0 * s.stride + j];
@@ -116,9 +120,8 @@ __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ sy
   while (P < 64 && 2 * P * n <= 256) P *= 2;
   const int per_pass = 256 / P;
   const int sub = tid % P;
-  const int64_t kend = k1 < (int64_t)s.total_steps ? k1 : (int64_t)s.total_steps;
   __syncthreads();
-  for (int64_t k = k0; k < kend; ++k) {
+  for (int64_t k = kl0; k < kl1; ++k) {
     const int cur = (int)(k & 1);
     const P4* mc = mom + (int64_t)cur * nmax;
     double mxsum = 0.0;
@@ -170,7 +173,6 @@ template <typename T, int TI>
 __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ systems,
                                                 const int2* __restrict__ tiles,
                                                 const int64_t* __restrict__ kbase, int64_t koff) {
-  const int64_t k = (kbase ? *kbase : 0) + koff;
   using P4 = typename V4<T>::type;
   constexpr int L = 64 / TI;      // streams per wave
   constexpr int Q = 16 * L;       // streams per block
@@ -180,7 +182,8 @@ __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ syst
   __shared__ T red[3][Q][TI];
   const int2 tl = tiles[blockIdx.x];
   const SysDesc& s = systems[tl.x];
-  if (k >= s.total_steps) return;
+  const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
+  if (k < 0 || k >= s.total_steps) return;
   const int n = s.n;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
@@ -246,11 +249,11 @@ __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ syst
 __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ systems,
                                                 const int2* __restrict__ blocks,
                                                 const int64_t* __restrict__ kbase, int64_t koff) {
-  const int64_t k = (kbase ? *kbase : 0) + koff;
   __shared__ double red[4];
   const int2 bl = blocks[blockIdx.x];
   const SysDesc& s = systems[bl.x];
-  if (k >= s.total_steps) return;
+  const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
+  if (k < 0 || k >= s.total_steps) return;
   const int i = bl.y * 256 + threadIdx.x;
   const int cur = (int)(k & 1);
   double mx = 0.0;

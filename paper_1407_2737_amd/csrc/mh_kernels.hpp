@@ -28,6 +28,7 @@ struct SysDesc {
   double* rec;       // loop record of the kept steps: sum_i m_x after each step
   double* sys_area;  // this system's loop area (J/m^3), written at the end of a run
   int64_t stride;    // distance between the two moment buffers (elements)
+  int64_t k_origin;  // global step at which this system's step 0 runs
   uint64_t seed, stream;
   NPParams np;
   double Bmax;       // mu0 Hmax (T)

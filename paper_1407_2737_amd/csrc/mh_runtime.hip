@@ -5,7 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -138,6 +143,8 @@ struct mh_asm {
   int Mp = 0, Kp = 0, Rp = 0;
   bool w_built = false;
   int state_parity = 0;  // the current moments live in buffer state_parity
+  int64_t k_origin = 0;    // global step of local step 0 (continuous batching)
+  uint64_t stream_base = 0;  // Philox stream of replica 0
   hipEvent_t done = nullptr;
   // host copy of the per-run system descriptors (for diagnostics re-runs)
 };
@@ -287,7 +294,8 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.diag = nullptr;
   s.stride = a->R * n;
   s.seed = a->seed;
-  s.stream = (uint64_t)r;
+  s.stream = a->stream_base + (uint64_t)r;
+  s.k_origin = a->k_origin;
   const double V = 3.14159265358979323846 * p.d * p.d * p.d / 6.0;
   s.np.BK = p.Keff > 0 ? 2.0 * p.Keff / p.Ms : 0.0;
   s.np.BK_inv = p.Keff > 0 ? p.Ms / (2.0 * p.Keff) : 0.0;
@@ -388,6 +396,7 @@ void timing_end(mh_ctx* c, hipStream_t st, int idx) {
 
 struct RunOpts {
   bool init = true;          // fresh run: initial moments, zero accumulators
+  bool sync32 = true;        // refresh FP32 moment copies (moments written from the host)
   int64_t k0 = 0, k1 = -1;   // step range (-1: to the end)
   bool finalize = true;
   bool field_only = false;
@@ -428,7 +437,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       } else {
         add_tiled(pl, fp64 ? 1 : 0, a->tile_kind, s);
       }
-      pl.kmax = std::max<int64_t>(pl.kmax, s.total_steps);
+      pl.kmax = std::max<int64_t>(pl.kmax, s.k_origin + s.total_steps);
       pl.nmax_all = std::max(pl.nmax_all, (int)a->n);
     }
     fin.push_back({a, {first, (int)all.size()}});
@@ -467,17 +476,18 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   int2* d_ublocks = stage_upload(c, pl.ublocks, off, st);
   if (o.init) {
     if (launch_init(d_all, (int)all.size(), pl.nmax_all, st) != hipSuccess) return MH_EDEVICE;
-  } else {
+  } else if (o.sync32) {
     // moments may have been replaced from the host: refresh the FP32 copies
     if (launch_sync32(d_all, (int)all.size(), pl.nmax_all, (int)(o.k0 & 1), st) != hipSuccess)
       return MH_EDEVICE;
   }
-  for (auto& it : pl.wm)
-    if (launch_wm_pack(d_all + it.first, (int)it.a->R, (int)it.a->n, it.g, (int)(o.k0 & 1), st) !=
-        hipSuccess)
-      return MH_EDEVICE;
+  if (o.init || o.sync32)
+    for (auto& it : pl.wm)
+      if (launch_wm_pack(d_all + it.first, (int)it.a->R, (int)it.a->n, it.g,
+                         (int)((o.k0 - it.a->k_origin) & 1), st) != hipSuccess)
+        return MH_EDEVICE;
   const int64_t k0 = o.k0;
-  const int64_t k1 = o.k1 < 0 ? pl.kmax : std::min<int64_t>(o.k1, pl.kmax);
+  const int64_t k1 = o.k1 < 0 ? pl.kmax : o.k1;
   const bool any_res = !pl.res64.empty() || !pl.res32.empty();
   bool any_til = !pl.wm.empty();
   for (int f = 0; f < 2; ++f)
@@ -579,7 +589,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       return MH_EDEVICE;
     if (hipEventRecord(a->done, st) != hipSuccess) return MH_EDEVICE;
     a->ran = true;
-    a->state_parity = (int)(std::min<int64_t>(k1, total_steps(a->p)) & 1);
+    a->state_parity = (int)(std::min<int64_t>(k1 - a->k_origin, total_steps(a->p)) & 1);
   }
   return MH_OK;
 }
@@ -968,6 +978,306 @@ int mh_debug_sw(mh_ctx* c, int64_t n, const double* hx, const double* hy, const 
     rc = MH_EDEVICE;
   (void)hipFree(d);
   return rc;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Continuous-batching server
+//
+// A scheduler thread keeps one global step clock. Every iteration it admits queued
+// requests in arrival order while their device memory fits the budget, then advances
+// every admitted request by one chunk of steps in a single fused launch sequence
+// (requests at different points of their runs share the launches; each reads its own
+// local step = clock - origin). A request runs in rounds of up to 64 replicas on
+// consecutive Philox streams; after each round the replica areas are appended on the
+// device and reduced, and the request finishes once 2 SE <= max(target |A|, 1e-3 2K)
+// with at least min_replicas, or at max_replicas. Its result depends only on its own
+// inputs: launch forms are chosen per assembly and every system has its own streams.
+// ===========================================================================
+namespace {
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct SReq {
+  uint64_t id = 0;
+  mh_asm* a = nullptr;
+  uint64_t seed = 0;
+  double target = 0.01;
+  int64_t minR = 64, maxR = 8192, done_R = 0, round_R = 0;
+  int state = 0;  // 0 queued, 1 running, 2 done
+  int64_t end = 0;
+  size_t bytes = 0;
+  DevBuf areas;  // per-replica areas of finished rounds
+  mh_result res{};
+};
+
+size_t request_bytes(int64_t n, const mh_params& p, int64_t R, int64_t maxR) {
+  const int64_t rows = (int64_t)(p.n_periods - p.n_discard) * p.steps_per_period;
+  const int64_t nt = (n + 255) / 256;
+  size_t b = (size_t)R * n * (2 * 32 + 2 * 16 + 16 + 32) + (size_t)R * rows * (nt + 1) * 8;
+  b += (size_t)n * (32 + 16 + 32) + (size_t)maxR * 8 + 4096;
+  if (p.precision == MH_BF16X3_WM) {
+    const int64_t rq = 8 * 96;
+    const int64_t Mp = (3 * n + rq - 1) / rq * rq, Kp = (3 * n + 63) / 64 * 64;
+    const int64_t Rp = (R + 255) / 256 * 256;
+    b += (size_t)Mp * Kp * 4 + (size_t)Rp * Kp * 4 + (size_t)Rp * Mp * 4;
+  }
+  return b;
+}
+
+}  // namespace
+
+struct mh_server {
+  mh_ctx* ctx = nullptr;
+  size_t budget = 0, used = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<SReq*> queue;
+  std::vector<SReq*> running;
+  std::unordered_map<uint64_t, SReq*> reqs;
+  uint64_t next_id = 1;
+  bool stop = false;
+  int64_t clock = 0;
+  int chunk = 50;
+  int64_t round_size = 64;
+  int error = 0;
+  std::thread th;
+  void loop();
+  int start_round(SReq* q);
+  int finish_round(SReq* q, bool& done);
+};
+
+int mh_server::start_round(SReq* q) {
+  // the matrix form pads replicas to 256 per product, so it runs rounds of 256
+  const int64_t rs = q->a->p.precision == MH_BF16X3_WM ? 4 * round_size : round_size;
+  q->round_R = std::min<int64_t>(rs, q->maxR - q->done_R);
+  q->a->k_origin = clock;
+  q->a->stream_base = (uint64_t)q->done_R;
+  std::vector<mh_asm*> v{q->a};
+  std::vector<int64_t> R{q->round_R};
+  std::vector<uint64_t> S{q->seed};
+  RunOpts o;
+  o.k0 = o.k1 = clock;
+  o.finalize = false;
+  const int e = run_systems(v, R, S, ctx->stream, o);
+  q->end = clock + total_steps(q->a->p);
+  q->state = 1;
+  return e;
+}
+
+int mh_server::finish_round(SReq* q, bool& done) {
+  std::vector<mh_asm*> v{q->a};
+  std::vector<int64_t> R{q->round_R};
+  std::vector<uint64_t> S{q->seed};
+  RunOpts o;
+  o.init = false;
+  o.sync32 = false;
+  o.k0 = o.k1 = clock;
+  int e = run_systems(v, R, S, ctx->stream, o);
+  if (e) return e;
+  hipStream_t st = ctx->stream;
+  if (hipMemcpyAsync(q->areas.as<double>() + q->done_R, q->a->sys_area.p,
+                     sizeof(double) * q->round_R, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return MH_EDEVICE;
+  q->done_R += q->round_R;
+  if (launch_finalize_asm(q->areas.as<double>(), (int)q->done_R, q->a->stats.as<double>(), st) !=
+      hipSuccess)
+    return MH_EDEVICE;
+  double stt[2];
+  if (hipMemcpyAsync(stt, q->a->stats.p, sizeof(stt), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return MH_EDEVICE;
+  const mh_params& p = q->a->p;
+  const double floor = 1e-3 * 2.0 * p.Keff;
+  const bool conv = q->done_R >= q->minR && 2.0 * stt[1] <= std::max(q->target * std::fabs(stt[0]), floor);
+  done = conv || q->done_R >= q->maxR;
+  if (done) {
+    q->res.area_Jm3 = stt[0];
+    q->res.area_se = stt[1];
+    q->res.sar_Wkg = stt[0] * p.f / p.rho;
+    q->res.sar_se = stt[1] * p.f / p.rho;
+    q->res.replicas = q->done_R;
+    q->res.loops = q->done_R * (p.n_periods - p.n_discard);
+    q->res.done_ns = now_ns();
+    q->res.status = std::isfinite(stt[0]) ? MH_OK : MH_ENUMERIC;
+  }
+  return MH_OK;
+}
+
+void mh_server::loop() {
+  if (set_dev(ctx)) {
+    error = MH_EDEVICE;
+    return;
+  }
+  for (;;) {
+    std::vector<SReq*> admit;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      while (!stop && queue.empty() && running.empty()) cv.wait(lk);
+      if (stop && running.empty() && queue.empty()) break;
+      if (stop) {  // drop queued work on shutdown
+        for (auto* q : queue) q->state = 2, q->res.status = MH_EINVAL;
+        queue.clear();
+      }
+      while (!queue.empty() && used + queue.front()->bytes <= budget) {
+        SReq* q = queue.front();
+        queue.pop_front();
+        used += q->bytes;
+        admit.push_back(q);
+      }
+    }
+    for (auto* q : admit) {
+      q->res.start_ns = now_ns();
+      int e = q->areas.ensure(sizeof(double) * q->maxR);
+      if (!e) e = start_round(q);
+      if (e) {
+        std::lock_guard<std::mutex> lk(mu);
+        q->state = 2;
+        q->res.status = e;
+        q->res.done_ns = now_ns();
+        used -= q->bytes;
+        continue;
+      }
+      running.push_back(q);
+    }
+    if (running.empty()) continue;
+    // one chunk of steps for every running request
+    std::vector<mh_asm*> v;
+    std::vector<int64_t> R;
+    std::vector<uint64_t> S;
+    for (auto* q : running) {
+      v.push_back(q->a);
+      R.push_back(q->round_R);
+      S.push_back(q->seed);
+    }
+    RunOpts o;
+    o.init = false;
+    o.sync32 = false;
+    o.finalize = false;
+    o.k0 = clock;
+    o.k1 = clock + chunk;
+    int e = run_systems(v, R, S, ctx->stream, o);
+    clock += chunk;
+    std::vector<SReq*> still;
+    for (auto* q : running) {
+      bool done = false;
+      if (!e && q->end <= clock) {
+        int e2 = finish_round(q, done);
+        if (!e2 && !done) e2 = start_round(q);
+        if (e2) {
+          done = true;
+          q->res.status = e2;
+          q->res.done_ns = now_ns();
+        }
+      } else if (e) {
+        done = true;
+        q->res.status = e;
+        q->res.done_ns = now_ns();
+      }
+      if (done) {
+        mh_destroy_assembly(q->a);
+        q->a = nullptr;
+        q->areas.release();
+        std::lock_guard<std::mutex> lk(mu);
+        q->state = 2;
+        used -= q->bytes;
+      } else {
+        still.push_back(q);
+      }
+    }
+    running.swap(still);
+  }
+}
+
+extern "C" {
+
+int mh_server_create(mh_ctx* ctx, size_t hbm_budget_bytes, mh_server** out) {
+  if (!ctx || !out || hbm_budget_bytes == 0) return MH_EINVAL;
+  mh_server* s = new (std::nothrow) mh_server();
+  if (!s) return MH_ENOMEM;
+  // a private context: the scheduler's stream, plan buffers and graphs are its own
+  int e = mh_ctx_create(ctx->device, &s->ctx);
+  if (e) {
+    delete s;
+    return e;
+  }
+  s->budget = hbm_budget_bytes;
+  s->th = std::thread([s] { s->loop(); });
+  *out = s;
+  return MH_OK;
+}
+
+int mh_server_submit(mh_server* s, const mh_request* rq, uint64_t* req_id) {
+  if (!s || !rq || !req_id) return MH_EINVAL;
+  if (rq->min_replicas < 1 || rq->max_replicas < rq->min_replicas || rq->max_replicas > (1 << 20) ||
+      !(rq->target_rel_err > 0))
+    return MH_EINVAL;
+  const int64_t rs = rq->params.precision == MH_BF16X3_WM ? 4 * s->round_size : s->round_size;
+  const int64_t R = std::min<int64_t>(rs, rq->max_replicas);
+  const size_t bytes = request_bytes(rq->n, rq->params, R, rq->max_replicas);
+  if (bytes > s->budget) return MH_EBUDGET;
+  mh_asm* a = nullptr;
+  int e = mh_create_assembly(s->ctx, rq->n, rq->pos, rq->axes, rq->n_axes_sets, &rq->params, &a);
+  if (e) return e;
+  SReq* q = new (std::nothrow) SReq();
+  if (!q) {
+    mh_destroy_assembly(a);
+    return MH_ENOMEM;
+  }
+  q->a = a;
+  q->seed = rq->seed;
+  q->target = rq->target_rel_err;
+  q->minR = rq->min_replicas;
+  q->maxR = rq->max_replicas;
+  q->bytes = bytes;
+  q->res.submit_ns = now_ns();
+  q->res.status = MH_ENOTREADY;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      mh_destroy_assembly(a);
+      delete q;
+      return MH_EINVAL;
+    }
+    q->id = s->next_id++;
+    s->reqs[q->id] = q;
+    s->queue.push_back(q);
+  }
+  s->cv.notify_one();
+  *req_id = q->id;
+  return MH_OK;
+}
+
+int mh_server_poll(mh_server* s, uint64_t req_id, mh_result* out) {
+  if (!s || !out) return MH_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->reqs.find(req_id);
+  if (it == s->reqs.end()) return MH_EINVAL;
+  if (it->second->state != 2) return MH_ENOTREADY;
+  *out = it->second->res;
+  return MH_OK;
+}
+
+int mh_server_destroy(mh_server* s) {
+  if (!s) return MH_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv.notify_one();
+  if (s->th.joinable()) s->th.join();
+  for (auto& kv : s->reqs) {
+    if (kv.second->a) mh_destroy_assembly(kv.second->a);
+    delete kv.second;
+  }
+  mh_ctx_destroy(s->ctx);
+  delete s;
+  return MH_OK;
 }
 
 }  // extern "C"

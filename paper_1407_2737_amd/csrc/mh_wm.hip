@@ -234,10 +234,10 @@ __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ s
                                                    const int64_t* __restrict__ kbase,
                                                    int64_t koff) {
   __shared__ double red[4];
-  const int64_t k = (kbase ? *kbase : 0) + koff;
   const int r = blockIdx.y;
   const SysDesc& s = systems[r];
-  if (k >= s.total_steps) return;
+  const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
+  if (k < 0 || k >= s.total_steps) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
   const int cur = (int)(k & 1);
   double mx = 0.0;

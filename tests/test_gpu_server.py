@@ -1,0 +1,80 @@
+"""Continuous-batching server: a request's result is the same alone and when it runs
+interleaved with other requests of different sizes and forms (it is also the same as a
+direct run of the same replicas), and requests that can never fit the device-memory
+budget are refused at submission."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1407_2737_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _req(lib, n, prec, seed, S=100, P=2):
+    d = 12e-9
+    R = d / 2 * (n / 0.05) ** (1 / 3)
+    pos = W.place_random(n, R, d, seed)
+    axes = W.axes_random_3d(n, seed + 1)
+    kw = dict(Ms=4e5, Keff=1.3e4, d=d, T=300.0, tau0=1e-10, rho=5200.0, f=1e5, mu0Hmax=0.02,
+              steps_per_period=S, n_periods=P, n_discard=1)
+    return pos, axes, lib.Params.make(prec, **kw)
+
+
+def _wait(srv, ids, timeout=240):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(ids):
+        for i in ids:
+            if i not in out:
+                r = srv.poll(i)
+                if r is not None:
+                    out[i] = r
+        assert time.time() - t0 < timeout, "server did not finish in time"
+        time.sleep(0.01)
+    return out
+
+
+def test_alone_equals_mix(lib):
+    ctx = lib.Context(0)
+    A = _req(lib, 150, lib.FP32_FIELD, 11)
+    srv = lib.Server(ctx, 8 << 30)
+    ia = srv.submit(*A, seed=7, target_rel_err=0.02, min_replicas=64, max_replicas=128)
+    alone = _wait(srv, [ia])[ia]
+    srv.close()
+    assert alone["status"] == 0 and alone["replicas"] in (64, 128)
+
+    srv = lib.Server(ctx, 8 << 30)
+    others = [_req(lib, 900, lib.FP32_FIELD, 21, S=60, P=3), _req(lib, 300, lib.BF16X3_WM, 31),
+              _req(lib, 60, lib.FP64, 41, S=140), _req(lib, 2000, lib.FP32_FIELD, 51, S=40)]
+    ids = [srv.submit(*others[0], seed=1, max_replicas=64),
+           srv.submit(*others[1], seed=2, max_replicas=256)]
+    time.sleep(0.05)                       # A arrives while the others run
+    ib = srv.submit(*A, seed=7, target_rel_err=0.02, min_replicas=64, max_replicas=128)
+    ids += [srv.submit(*others[2], seed=3, max_replicas=64),
+            srv.submit(*others[3], seed=4, max_replicas=64)]
+    res = _wait(srv, ids + [ib])
+    srv.close()
+    mix = res[ib]
+    for key in ("area_Jm3", "area_se", "sar_Wkg", "sar_se", "replicas", "loops", "status"):
+        assert mix[key] == alone[key], (key, mix[key], alone[key])
+    assert all(res[i]["status"] == 0 for i in ids)
+    assert mix["start_ns"] >= mix["submit_ns"] and mix["done_ns"] > mix["start_ns"]
+
+    # the same replicas run directly give the same area
+    a = lib.Assembly(ctx, A[0], A[1], A[2])
+    a.run(alone["replicas"], seed=7)
+    a.sync()
+    direct = a.sar()
+    assert direct["area"] == alone["area_Jm3"] and direct["area_se"] == alone["area_se"]
+
+
+def test_budget_refusal(lib):
+    ctx = lib.Context(0)
+    srv = lib.Server(ctx, 1 << 20)          # 1 MiB
+    pos, axes, p = _req(lib, 2000, lib.FP32_FIELD, 61)
+    with pytest.raises(lib.MHError) as e:
+        srv.submit(pos, axes, p, seed=1)
+    assert e.value.code == -7
+    srv.close()
