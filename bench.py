@@ -54,7 +54,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c4plain"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c4plain", "c5", "c5wm"])
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--max-replicas", type=int, default=64)
     ap.add_argument("--assemblies", type=int, default=256)
     ap.add_argument("--replicas", type=int, default=512)
     args = ap.parse_args()
@@ -69,6 +71,8 @@ def main():
 
     if args.workload == "c3":
         return bench_c3(args, mh, W)
+    if args.workload in ("c5", "c5wm"):
+        return bench_c5(args, mh, W)
     if args.workload != "c2":
         return bench_c4(args, mh, W)
 
@@ -136,6 +140,80 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(work)
+    print(json.dumps(line), flush=True)
+
+
+def bench_c5(args, mh, W):
+    """Serving: loop-simulation requests with N log-uniform in [100, 8000], radius
+    U(80,300) nm, phi U(1,20) %, f log-uniform in [1e5, 1e6] Hz, Hmax U(5,50) mT, 3-10
+    periods (one discarded). Phase 1 submits the first quarter at once to measure the
+    saturated request rate; phase 2 submits the rest as a Poisson stream at 0.7 of it.
+    Each request runs rounds of replicas until 2 SE <= max(1 % |A|, 1e-3 2K) or
+    --max-replicas."""
+    import numpy as np
+    prec = mh.BF16X3_WM if args.workload == "c5wm" else mh.FP32_FIELD
+    reqs = W.config5_requests(count=args.requests, seed=1005, rate_hz=1.0)
+    inputs = []
+    for q in reqs:
+        Rl = q["R"]
+        pos = W.place_random(q["n"], Rl, q["d"], q["seed"])
+        axes = W.axes_random_3d(q["n"], q["seed"] + 1)
+        p = mh.Params.make(prec, Ms=4e5, Keff=1.3e4, d=q["d"], T=300.0, tau0=1e-10, rho=5200.0,
+                           f=q["f"], mu0Hmax=q["H"], steps_per_period=2000, n_periods=q["P"],
+                           n_discard=1)
+        inputs.append((pos, axes, p, q))
+    ctx = mh.Context(0)
+    srv = mh.Server(ctx, 200 << 30)
+    maxr = args.max_replicas if prec == mh.FP32_FIELD else max(args.max_replicas, 256)
+
+    def drain(ids, out):
+        while any(i not in out for i in ids):
+            for i in ids:
+                if i not in out:
+                    r = srv.poll(i)
+                    if r is not None:
+                        out[i] = r
+            time.sleep(0.002)
+
+    n1 = max(1, len(inputs) // 4)
+    t0 = time.perf_counter()
+    ids1 = [srv.submit(x[0], x[1], x[2], seed=x[3]["seed"], target_rel_err=0.01,
+                       min_replicas=64, max_replicas=maxr) for x in inputs[:n1]]
+    res = {}
+    drain(ids1, res)
+    sat_rate = n1 / (time.perf_counter() - t0)
+    lam = 0.7 * sat_rate
+    rng = np.random.default_rng(77)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(inputs) - n1))
+    ids2 = []
+    t1 = time.perf_counter()
+    for x, ta in zip(inputs[n1:], arrivals):
+        while time.perf_counter() - t1 < ta:
+            time.sleep(0.0005)
+        ids2.append(srv.submit(x[0], x[1], x[2], seed=x[3]["seed"], target_rel_err=0.01,
+                               min_replicas=64, max_replicas=maxr))
+    drain(ids2, res)
+    t2 = time.perf_counter()
+    srv.close()
+    lat = np.array([(res[i]["done_ns"] - res[i]["submit_ns"]) / 1e9 for i in ids2])
+    loops = sum(res[i]["loops"] for i in ids2)
+    npsteps = sum(x[0].shape[0] * 2000 * x[3]["P"] * res[i]["replicas"] for x, i in zip(inputs[n1:], ids2))
+    rel = [2 * res[i]["area_se"] / max(abs(res[i]["area_Jm3"]), 1e-300) for i in ids2]
+    line = {"metric": "served loops/s; p50/p99 request latency", "value": loops / (t2 - t1),
+            "unit": "loops/s", "n_gpus": 1, "steps": len(ids2), "warmup": n1,
+            "ms_per_step": (t2 - t1) / max(len(ids2), 1) * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16x3 mfma / f64 barrier" if prec == mh.BF16X3_WM else "f32 field / f64 barrier",
+            "data": "synthetic",
+            "config": {"workload": f"config5 ({args.workload}): Poisson arrivals at 0.7 x saturated rate "
+                                   f"({lam:.3f} req/s), {len(ids2)} timed requests after {n1} saturation ones",
+                       "p50_latency_s": float(np.percentile(lat, 50)),
+                       "p99_latency_s": float(np.percentile(lat, 99)),
+                       "np_steps_per_s": npsteps / (t2 - t1),
+                       "saturated_req_per_s": sat_rate,
+                       "replicas_per_request_median": float(np.median([res[i]["replicas"] for i in ids2])),
+                       "two_se_over_area_median": float(np.median(rel)),
+                       "max_replicas": maxr}}
     print(json.dumps(line), flush=True)
 
 
