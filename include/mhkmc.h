@@ -98,6 +98,11 @@ int mh_destroy_assembly(mh_asm* a);
  * respect to the host; results are read after mh_sync. */
 int mh_run_loops(mh_asm* a, int64_t n_replicas, uint64_t seed, void* hip_stream);
 
+/* Per-replica field amplitudes for later runs: replica r uses mu0Hmax[r mod count]
+ * (T) instead of params.mu0Hmax, e.g. an amplitude sweep on one lysosome
+ * (Sec. III.2.b). count = 0 restores params.mu0Hmax. */
+int mh_set_replica_fields(mh_asm* a, int64_t count, const double* mu0Hmax);
+
 /* Runs several assemblies together (uneven sizes, different materials and fields):
  * one fused launch per step covers every assembly that still has steps to run, and
  * small assemblies run all their steps inside one launch. Each assembly's results are

@@ -25,6 +25,7 @@ SYMBOLS = [
     "mh_get_replica_areas", "mh_get_moments", "mh_debug_steps", "mh_debug_philox",
     "mh_debug_sw", "mh_debug_field", "mh_strerror", "mh_ctx_set_timing", "mh_ctx_get_timing",
     "mh_server_create", "mh_server_submit", "mh_server_poll", "mh_server_destroy",
+    "mh_set_replica_fields",
 ]
 
 
@@ -103,6 +104,7 @@ def _lib():
             "mh_server_submit": ([vp, C.POINTER(Request), C.POINTER(u64)], C.c_int),
             "mh_server_poll": ([vp, u64, C.POINTER(Result)], C.c_int),
             "mh_server_destroy": ([vp], C.c_int),
+            "mh_set_replica_fields": ([vp, i64, dp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -197,6 +199,12 @@ class Assembly:
             self.close()
         except Exception:
             pass
+
+    def set_replica_fields(self, mu0Hmax):
+        """Per-replica field amplitudes (T); replica r uses mu0Hmax[r mod len]."""
+        h = _f64(mu0Hmax).ravel()
+        _check(_lib().mh_set_replica_fields(self._h, h.shape[0], _dp(h) if h.size else None),
+               "mh_set_replica_fields")
 
     def run(self, n_replicas: int = 1, seed: int = 0, stream=None):
         _check(_lib().mh_run_loops(self._h, n_replicas, seed, stream), "mh_run_loops")

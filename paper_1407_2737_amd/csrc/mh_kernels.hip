@@ -169,22 +169,23 @@ __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ sy
 //
 // k_update, one thread per particle: steps iii-vii and the accumulations.
 // ---------------------------------------------------------------------------
-template <typename T, int TI>
+template <typename T, int TI, int G>
 __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ systems,
-                                                const int2* __restrict__ tiles,
+                                                const int4* __restrict__ tiles,
                                                 const int64_t* __restrict__ kbase, int64_t koff) {
   using P4 = typename V4<T>::type;
-  constexpr int L = 64 / TI;      // streams per wave
-  constexpr int Q = 16 * L;       // streams per block
-  constexpr int CH = 1024;        // sources per staged chunk
+  constexpr int L = 64 / TI;                       // streams per wave
+  constexpr int Q = 16 * L;                        // streams per block
+  constexpr int CH = G == 1 ? 1024 : 512;          // sources per staged chunk
   __shared__ P4 spos[CH];
-  __shared__ P4 smom[CH];
-  __shared__ T red[3][Q][TI];
-  const int2 tl = tiles[blockIdx.x];
+  __shared__ P4 smom[G][CH];
+  __shared__ T red[3][G][Q][TI];
+  const int4 tl = tiles[blockIdx.x];               // (first system, i-tile, replicas, part)
   const SysDesc& s = systems[tl.x];
   const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;
   const int n = s.n;
+  const int gn = tl.z;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int il = l % TI;
@@ -192,57 +193,109 @@ __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ syst
   const int i = tl.y * TI + il;
   const int cur = (int)(k & 1);
   const P4* gpos = pos_of<T>(s);
-  const P4* gmom = mom_of<T>(s) + (int64_t)cur * s.stride;
-  T bx = 0, by = 0, bz = 0;
+  const P4* gmom[G];
+#pragma unroll
+  for (int r = 0; r < G; ++r)
+    gmom[r] = mom_of<T>(systems[tl.x + (r < gn ? r : 0)]) + (int64_t)cur * s.stride;
+  T bx[G], by[G], bz[G];
+#pragma unroll
+  for (int r = 0; r < G; ++r) bx[r] = by[r] = bz[r] = (T)0;
+  // sources of this block: part tl.w of nsplit equal parts (multiples of Q)
+  const int per = ((n + s.nsplit - 1) / s.nsplit + Q - 1) / Q * Q;
+  const int jb = tl.w * per, je = min(n, jb + per);
   if (s.Bscale != 0.0 && n > 1) {
     const P4 pi = gpos[i < n ? i : n - 1];
     const T xi = (T)pi.x, yi = (T)pi.y, zi = (T)pi.z;
-    for (int c0 = 0; c0 < n; c0 += CH) {
-      const int cn = min(CH, n - c0);
+    for (int c0 = jb; c0 < je; c0 += CH) {
+      const int cn = min(CH, je - c0);
       __syncthreads();
       for (int j = tid; j < CH; j += 1024) {
-        P4 p, m;
+        P4 p;
         if (j < cn) {
           p = gpos[c0 + j];
-          m = gmom[c0 + j];
         } else {  // padding: far away and without moment, contributes exactly zero
           p.x = p.y = p.z = (T)1e15;
-          m.x = m.y = m.z = (T)0;
-          p.w = m.w = (T)0;
+          p.w = (T)0;
         }
         spos[j] = p;
-        smom[j] = m;
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+          P4 m;
+          if (j < cn && r < gn) {
+            m = gmom[r][c0 + j];
+          } else {
+            m.x = m.y = m.z = m.w = (T)0;
+          }
+          smom[r][j] = m;
+        }
       }
       __syncthreads();
       const int ce = (cn + Q - 1) / Q * Q;  // streams stay in lockstep over padded entries
       // only the chunk holding this block's targets can contain j == i
       const bool self = (tl.y * TI < c0 + cn) && (tl.y * TI + TI > c0);
-      if (self) {
+      if (G == 1) {
+        if (self) {
 #pragma unroll 4
-        for (int e = q; e < ce; e += Q) dip_pair<T, true>(xi, yi, zi, spos[e], smom[e], bx, by, bz);
+          for (int e = q; e < ce; e += Q)
+            dip_pair<T, true>(xi, yi, zi, spos[e], smom[0][e], bx[0], by[0], bz[0]);
+        } else {
+#pragma unroll 4
+          for (int e = q; e < ce; e += Q)
+            dip_pair<T, false>(xi, yi, zi, spos[e], smom[0][e], bx[0], by[0], bz[0]);
+        }
       } else {
-#pragma unroll 4
-        for (int e = q; e < ce; e += Q) dip_pair<T, false>(xi, yi, zi, spos[e], smom[e], bx, by, bz);
+        // geometry once per pair, applied to the G replicas' moments
+#pragma unroll 2
+        for (int e = q; e < ce; e += Q) {
+          const P4 pj = spos[e];
+          const T dx = (T)pj.x - xi, dy = (T)pj.y - yi, dz = (T)pj.z - zi;
+          const T r2 = dx * dx + dy * dy + dz * dz;
+          T inv;
+          if constexpr (sizeof(T) == 4)
+            inv = rsqrtf(r2);
+          else
+            inv = (T)1 / sqrt(r2);
+          if (self) inv = r2 > (T)0 ? inv : (T)0;
+          const T inv2 = inv * inv;
+          const T inv3 = inv2 * inv;
+          const T s3 = (T)3 * inv2;
+#pragma unroll
+          for (int r = 0; r < G; ++r) {
+            const P4 mj = smom[r][e];
+            const T md = ((T)mj.x * dx + (T)mj.y * dy + (T)mj.z * dz) * s3;
+            bx[r] += inv3 * (md * dx - (T)mj.x);
+            by[r] += inv3 * (md * dy - (T)mj.y);
+            bz[r] += inv3 * (md * dz - (T)mj.z);
+          }
+        }
       }
     }
   }
-  red[0][q][il] = bx;
-  red[1][q][il] = by;
-  red[2][q][il] = bz;
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    red[0][r][q][il] = bx[r];
+    red[1][r][q][il] = by[r];
+    red[2][r][q][il] = bz[r];
+  }
   __syncthreads();
-  if (tid < TI && i < n) {
-    double ax = 0, ay = 0, az = 0;
-    for (int qq = 0; qq < Q; ++qq) {
-      ax += (double)red[0][qq][tid];
-      ay += (double)red[1][qq][tid];
-      az += (double)red[2][qq][tid];
+  // fixed-order FP64 reduction over the streams: thread (r, target) for r < gn
+  if (tid < G * TI) {
+    const int r = tid / TI, t = tid % TI;
+    const int ii = tl.y * TI + t;
+    if (r < gn && ii < n) {
+      double ax = 0, ay = 0, az = 0;
+      for (int qq = 0; qq < Q; ++qq) {
+        ax += (double)red[0][r][qq][t];
+        ay += (double)red[1][r][qq][t];
+        az += (double)red[2][r][qq][t];
+      }
+      D4 f;
+      f.x = ax;
+      f.y = ay;
+      f.z = az;
+      f.w = 0.0;
+      systems[tl.x + r].field[(int64_t)tl.w * n + ii] = f;
     }
-    D4 f;
-    f.x = ax;
-    f.y = ay;
-    f.z = az;
-    f.w = 0.0;
-    s.field[i] = f;
   }
 }
 
@@ -258,8 +311,14 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
   const int cur = (int)(k & 1);
   double mx = 0.0;
   if (i < s.n) {
-    const D4 f = s.field[i];
-    mx = np_epilogue(s, i, k, cur, f.x, f.y, f.z);
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int p = 0; p < s.nsplit; ++p) {  // partial sums of the source parts, fixed order
+      const D4 f = s.field[(int64_t)p * s.n + i];
+      fx += f.x;
+      fy += f.y;
+      fz += f.z;
+    }
+    mx = np_epilogue(s, i, k, cur, fx, fy, fz);
   }
   if (k >= s.kept0 && !s.field_only) {
     const double tot = block_sum_256(mx, red);
@@ -420,26 +479,41 @@ hipError_t set_resident_lds_limit() {
 
 int tile_width(int kind) { return kind == 0 ? 64 : 16; }
 
-// kind 0: 64 targets per field block, kind 1: 16 targets per field block
-// The step index is *kbase + koff (kbase may be null): a captured graph of G steps
-// reads a device-side base that its last node advances by G.
-hipError_t launch_field(bool fp64, int kind, const SysDesc* d_sys, const int2* d_tiles, int ntiles,
-                        const int64_t* kbase, int64_t koff, hipStream_t st) {
+// kind 0: 64 targets per field block, kind 1: 16 targets per field block; G replicas
+// of one assembly share each block (FP32 only for G > 1)
+template <typename T, int TI>
+static void launch_field_g(int G, const SysDesc* d_sys, const int4* d_tiles, int ntiles,
+                           const int64_t* kbase, int64_t koff, hipStream_t st) {
+  switch (G) {
+    case 4:
+      hipLaunchKernelGGL((k_field<T, TI, 4>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, kbase, koff);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_field<T, TI, 3>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, kbase, koff);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_field<T, TI, 2>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, kbase, koff);
+      break;
+    default:
+      hipLaunchKernelGGL((k_field<T, TI, 1>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles, kbase, koff);
+  }
+}
+
+hipError_t launch_field(bool fp64, int kind, int G, const SysDesc* d_sys, const int4* d_tiles,
+                        int ntiles, const int64_t* kbase, int64_t koff, hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
   if (fp64) {
     if (kind == 0)
-      hipLaunchKernelGGL((k_field<double, 64>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
+      hipLaunchKernelGGL((k_field<double, 64, 1>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
                          kbase, koff);
     else
-      hipLaunchKernelGGL((k_field<double, 16>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
+      hipLaunchKernelGGL((k_field<double, 16, 1>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
                          kbase, koff);
   } else {
     if (kind == 0)
-      hipLaunchKernelGGL((k_field<float, 64>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
-                         kbase, koff);
+      launch_field_g<float, 64>(G, d_sys, d_tiles, ntiles, kbase, koff, st);
     else
-      hipLaunchKernelGGL((k_field<float, 16>), dim3(ntiles), dim3(1024), 0, st, d_sys, d_tiles,
-                         kbase, koff);
+      launch_field_g<float, 16>(G, d_sys, d_tiles, ntiles, kbase, koff, st);
   }
   return hipGetLastError();
 }

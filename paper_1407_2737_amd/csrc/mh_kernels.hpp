@@ -24,7 +24,7 @@ struct SysDesc {
   double* area;      // per-particle area accumulators: [n] sums then [n] compensations
   double* recpart;   // loop record partial sums [n_kept * S][ntiles]
   double* diag;      // optional per-particle diagnostics (8 doubles each) or null
-  D4* field;         // reduced dipolar sum per particle, written by the field kernel
+  D4* field;         // reduced dipolar sums, nsplit partial sums per particle ([part][n])
   double* rec;       // loop record of the kept steps: sum_i m_x after each step
   double* sys_area;  // this system's loop area (J/m^3), written at the end of a run
   int64_t stride;    // distance between the two moment buffers (elements)
@@ -38,7 +38,7 @@ struct SysDesc {
   int32_t ntiles;    // update blocks of 256 particles (1 for the resident kernel)
   int32_t S, total_steps, kept0, static_field;
   int32_t field_only;  // diagnostics: write the dipolar field to diag, change nothing
-  int32_t pad_;
+  int32_t nsplit;      // source parts of the tiled field sum (partials summed by the update)
 };
 
 // Operands of the interaction-matrix product (see mh_wm.hip).

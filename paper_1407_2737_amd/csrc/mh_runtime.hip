@@ -26,8 +26,8 @@ hipError_t launch_resident(bool fp64, const SysDesc* d_sys, int nsys, int64_t k0
 size_t resident_lds_bytes(bool fp64, int nmax);
 hipError_t set_resident_lds_limit();
 int tile_width(int kind);
-hipError_t launch_field(bool fp64, int kind, const SysDesc* d_sys, const int2* d_tiles, int ntiles,
-                        const int64_t* kbase, int64_t koff, hipStream_t st);
+hipError_t launch_field(bool fp64, int kind, int G, const SysDesc* d_sys, const int4* d_tiles,
+                        int ntiles, const int64_t* kbase, int64_t koff, hipStream_t st);
 hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks,
                          const int64_t* kbase, int64_t koff, hipStream_t st);
 hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st);
@@ -137,6 +137,7 @@ struct mh_asm {
   int ntiles = 1;
   int resident = 0;
   int tile_kind = 0;  // 0: 64 targets per block, 1: 16
+  int nsplit = 1;     // source parts per field tile
   DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp, field;
   // interaction-matrix form: W hi/lo (Mp x Kp), M^T hi/lo (Rp x Kp), B^T (Rp x Mp)
   DevBuf whi, wlo, mhi, mlo, bt;
@@ -144,6 +145,7 @@ struct mh_asm {
   bool w_built = false;
   int state_parity = 0;  // the current moments live in buffer state_parity
   int64_t k_origin = 0;    // global step of local step 0 (continuous batching)
+  std::vector<double> hmax;  // per-replica field amplitudes (replica r uses r mod size)
   uint64_t stream_base = 0;  // Philox stream of replica 0
   hipEvent_t done = nullptr;
   // host copy of the per-run system descriptors (for diagnostics re-runs)
@@ -224,7 +226,20 @@ bool wants_resident(const mh_asm* a, int64_t R) {
 // Field tile width: 64 targets per block once the assembly's own blocks fill the
 // device, else 16 (four times more blocks).
 int tile_kind_for(const mh_asm* a, int64_t R) {
-  return R * ((a->n + 63) / 64) >= a->ctx->n_cu ? 0 : 1;
+  const int64_t groups = a->p.precision == MH_FP64 ? R : (R + 3) / 4;
+  return groups * ((a->n + 63) / 64) >= a->ctx->n_cu ? 0 : 1;
+}
+
+// Source parts per field tile: enough blocks for about four per CU (load balance),
+// with parts of at least 1250 sources so that every block keeps enough work to cover
+// its staging and reduction.
+int nsplit_for(const mh_asm* a, int64_t R, int kind) {
+  const int64_t groups = a->p.precision == MH_FP64 ? R : (R + 3) / 4;
+  const int64_t TI = kind == 0 ? 64 : 16;
+  const int64_t blocks = groups * ((a->n + TI - 1) / TI);
+  int64_t sp = (4 * a->ctx->n_cu + blocks - 1) / blocks;
+  sp = std::min<int64_t>(sp, std::max<int64_t>(1, a->n / 1250));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(sp, 16));
 }
 
 // (Re)allocate a replica set and its per-run buffers.
@@ -232,6 +247,7 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   const int64_t n = a->n;
   a->resident = resident ? 1 : 0;
   a->tile_kind = tile_kind;
+  a->nsplit = resident ? 1 : nsplit_for(a, R, tile_kind);
   a->ntiles = resident ? 1 : (int)((n + 255) / 256);
   const int64_t rows = (int64_t)n_kept(a->p) * a->p.steps_per_period;
   int e;
@@ -243,7 +259,7 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   if ((e = a->sys_area.ensure(sizeof(double) * R))) return e;
   if ((e = a->stats.ensure(sizeof(double) * 4))) return e;
   const bool wm = a->p.precision == MH_BF16X3_WM;
-  if (!resident && !wm && (e = a->field.ensure(sizeof(D4) * R * n))) return e;
+  if (!resident && !wm && (e = a->field.ensure(sizeof(D4) * R * n * a->nsplit))) return e;
   if (wm) {
     if (!a->w_built) {
       const int64_t rows = 3 * n;
@@ -289,7 +305,8 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   const int64_t rows = (int64_t)n_kept(p) * p.steps_per_period;
   s.recpart = a->recpart.as<double>() + r * rows * a->ntiles;
   s.rec = a->rec.as<double>() + r * rows;
-  s.field = a->resident ? nullptr : a->field.as<D4>() + r * n;
+  s.field = a->resident ? nullptr : a->field.as<D4>() + r * n * a->nsplit;
+  s.nsplit = a->nsplit;
   s.sys_area = a->sys_area.as<double>() + r;
   s.diag = nullptr;
   s.stride = a->R * n;
@@ -305,7 +322,7 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.np.prob_form = p.prob_form;
   s.np.thermal = p.T > 0 ? 1 : 0;
   s.np.aniso = p.Keff > 0 ? 1 : 0;
-  s.Bmax = p.mu0Hmax;
+  s.Bmax = a->hmax.empty() ? p.mu0Hmax : a->hmax[(size_t)(r % (int64_t)a->hmax.size())];
   s.Bscale = p.interactions ? kMu0 * p.Ms / 24.0 : 0.0;
   s.Ms = p.Ms;
   s.n = (int32_t)n;
@@ -339,9 +356,13 @@ struct WMItem {
   WMArgs g;
 };
 
+// field launch groups: precision x tile kind x replicas per block (1..4)
+constexpr int kGroups = 2 * 2 * 4;
+inline int gidx(int fp64, int kind, int G) { return (fp64 * 2 + kind) * 4 + (G - 1); }
+
 struct Plan {
-  std::vector<SysDesc> res64, res32, til[2][2];  // til[fp64][kind]
-  std::vector<int2> tiles[2][2];
+  std::vector<SysDesc> res64, res32, til[kGroups];
+  std::vector<int4> tiles[kGroups];
   std::vector<WMItem> wm;
   std::vector<SysDesc> upd;   // all tiled systems
   std::vector<int2> ublocks;  // (system in upd, block of 256 particles)
@@ -350,14 +371,27 @@ struct Plan {
   int nmax_all = 0;
 };
 
-void add_tiled(Plan& pl, int fp64, int kind, const SysDesc& s) {
-  const int sidx = (int)pl.til[fp64][kind].size();
-  pl.til[fp64][kind].push_back(s);
+// The R replicas of one tiled assembly: field blocks take up to 4 replicas at a time in
+// FP32 (they share positions, so the pair geometry is computed once for all of them).
+void add_tiled(Plan& pl, int fp64, int kind, const std::vector<SysDesc>& reps) {
+  const int R = (int)reps.size();
   const int TI = tile_width(kind);
-  for (int it = 0; it < (s.n + TI - 1) / TI; ++it) pl.tiles[fp64][kind].push_back(int2{sidx, it});
-  const int uidx = (int)pl.upd.size();
-  pl.upd.push_back(s);
-  for (int b = 0; b < s.ntiles; ++b) pl.ublocks.push_back(int2{uidx, b});
+  const int Gmax = fp64 ? 1 : 4;
+  for (int g0 = 0; g0 < R; g0 += Gmax) {
+    const int gn = std::min(Gmax, R - g0);
+    const int gi = gidx(fp64, kind, gn);
+    const int sidx = (int)pl.til[gi].size();
+    for (int r = 0; r < gn; ++r) pl.til[gi].push_back(reps[g0 + r]);
+    const int n = reps[0].n;
+    for (int it = 0; it < (n + TI - 1) / TI; ++it)
+      for (int part = 0; part < reps[0].nsplit; ++part)
+        pl.tiles[gi].push_back(int4{sidx, it, gn, part});
+  }
+  for (const SysDesc& s : reps) {
+    const int uidx = (int)pl.upd.size();
+    pl.upd.push_back(s);
+    for (int b = 0; b < s.ntiles; ++b) pl.ublocks.push_back(int2{uidx, b});
+  }
 }
 
 // Descriptor array for a group, uploaded through the pinned stage into the device
@@ -423,6 +457,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     }
     const bool fp64 = a->p.precision == MH_FP64;
     const int first = (int)all.size();
+    std::vector<SysDesc> reps;
     for (int64_t r = 0; r < a->R; ++r) {
       SysDesc s = make_desc(a, r);
       s.field_only = o.field_only ? 1 : 0;
@@ -435,11 +470,12 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
         int& nm = fp64 ? pl.nmax_res64 : pl.nmax_res32;
         nm = std::max(nm, (int)a->n);
       } else {
-        add_tiled(pl, fp64 ? 1 : 0, a->tile_kind, s);
+        reps.push_back(s);
       }
       pl.kmax = std::max<int64_t>(pl.kmax, s.k_origin + s.total_steps);
       pl.nmax_all = std::max(pl.nmax_all, (int)a->n);
     }
+    if (!reps.empty()) add_tiled(pl, fp64 ? 1 : 0, a->tile_kind, reps);
     fin.push_back({a, {first, (int)all.size()}});
     if (a->p.precision == MH_BF16X3_WM) pl.wm.push_back(WMItem{a, first, wm_args(a)});
   }
@@ -449,11 +485,10 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   add(sizeof(SysDesc) * all.size());
   add(sizeof(SysDesc) * pl.res64.size());
   add(sizeof(SysDesc) * pl.res32.size());
-  for (int f = 0; f < 2; ++f)
-    for (int kd = 0; kd < 2; ++kd) {
-      add(sizeof(SysDesc) * pl.til[f][kd].size());
-      add(sizeof(int2) * pl.tiles[f][kd].size());
-    }
+  for (int gi = 0; gi < kGroups; ++gi) {
+    add(sizeof(SysDesc) * pl.til[gi].size());
+    add(sizeof(int4) * pl.tiles[gi].size());
+  }
   add(sizeof(SysDesc) * pl.upd.size());
   add(sizeof(int2) * pl.ublocks.size());
   bytes += 256;
@@ -465,13 +500,12 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   SysDesc* d_all = stage_upload(c, all, off, st);
   SysDesc* d_res64 = stage_upload(c, pl.res64, off, st);
   SysDesc* d_res32 = stage_upload(c, pl.res32, off, st);
-  SysDesc* d_til[2][2];
-  int2* d_tiles[2][2];
-  for (int f = 0; f < 2; ++f)
-    for (int kd = 0; kd < 2; ++kd) {
-      d_til[f][kd] = stage_upload(c, pl.til[f][kd], off, st);
-      d_tiles[f][kd] = stage_upload(c, pl.tiles[f][kd], off, st);
-    }
+  SysDesc* d_til[kGroups];
+  int4* d_tiles[kGroups];
+  for (int gi = 0; gi < kGroups; ++gi) {
+    d_til[gi] = stage_upload(c, pl.til[gi], off, st);
+    d_tiles[gi] = stage_upload(c, pl.tiles[gi], off, st);
+  }
   SysDesc* d_upd = stage_upload(c, pl.upd, off, st);
   int2* d_ublocks = stage_upload(c, pl.ublocks, off, st);
   if (o.init) {
@@ -489,9 +523,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   const int64_t k0 = o.k0;
   const int64_t k1 = o.k1 < 0 ? pl.kmax : o.k1;
   const bool any_res = !pl.res64.empty() || !pl.res32.empty();
-  bool any_til = !pl.wm.empty();
-  for (int f = 0; f < 2; ++f)
-    for (int kd = 0; kd < 2; ++kd) any_til = any_til || !pl.tiles[f][kd].empty();
+  bool any_til = !pl.wm.empty() || !pl.ublocks.empty();
   int tq = any_res && k1 > k0 ? timing_begin(c, st, 1) : -1;
   if (launch_resident(true, d_res64, (int)pl.res64.size(), k0, k1, pl.nmax_res64, st) != hipSuccess)
     return MH_EDEVICE;
@@ -504,9 +536,12 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     int t0 = timing_begin(c, st, 0);
     for (int f = 0; f < 2; ++f)
       for (int kd = 0; kd < 2; ++kd)
-        if (launch_field(f == 1, kd, d_til[f][kd], d_tiles[f][kd], (int)pl.tiles[f][kd].size(), kb,
-                         koff, st) != hipSuccess)
-          return MH_EDEVICE;
+        for (int G = 1; G <= 4; ++G) {
+          const int gi = gidx(f, kd, G);
+          if (launch_field(f == 1, kd, G, d_til[gi], d_tiles[gi], (int)pl.tiles[gi].size(), kb,
+                           koff, st) != hipSuccess)
+            return MH_EDEVICE;
+        }
     timing_end(c, st, t0);
     t0 = timing_begin(c, st, 3);
     if (launch_update(d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st) != hipSuccess)
@@ -532,11 +567,10 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     // the captured kernels read the plan from d_sys at fixed offsets: reuse the graph
     // while the uploaded plan has the same layout
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)c->d_sys.p, (uint64_t)off, (uint64_t)G};
-    for (int f = 0; f < 2; ++f)
-      for (int kd = 0; kd < 2; ++kd) {
-        key.push_back((uint64_t)(uintptr_t)d_til[f][kd]);
-        key.push_back(pl.tiles[f][kd].size());
-      }
+    for (int gi = 0; gi < kGroups; ++gi) {
+      key.push_back((uint64_t)(uintptr_t)d_til[gi]);
+      key.push_back(pl.tiles[gi].size());
+    }
     key.push_back((uint64_t)(uintptr_t)d_upd);
     key.push_back(pl.ublocks.size());
     for (auto& it : pl.wm) {
@@ -740,6 +774,14 @@ int mh_destroy_assembly(mh_asm* a) {
   return MH_OK;
 }
 
+int mh_set_replica_fields(mh_asm* a, int64_t count, const double* mu0Hmax) {
+  if (!a || count < 0 || (count > 0 && !mu0Hmax)) return MH_EINVAL;
+  for (int64_t q = 0; q < count; ++q)
+    if (!std::isfinite(mu0Hmax[q]) || mu0Hmax[q] < 0) return MH_EINVAL;
+  a->hmax.assign(mu0Hmax, mu0Hmax + count);
+  return MH_OK;
+}
+
 int mh_run_batch(mh_asm* const* asms, int32_t count, const int64_t* n_replicas,
                  const uint64_t* seeds, void* hip_stream) {
   if (!asms || count < 1 || !n_replicas || !seeds) return MH_EINVAL;
@@ -781,12 +823,14 @@ int mh_get_loop(mh_asm* a, int64_t replica, int32_t period, double* H_T, double*
                 sizeof(double) * S, hipMemcpyDeviceToHost) != hipSuccess)
     return MH_EDEVICE;
   const double scale = a->p.Ms / (double)a->n;
+  const double hm =
+      a->hmax.empty() ? a->p.mu0Hmax : a->hmax[(size_t)(replica % (int64_t)a->hmax.size())];
   for (int k = 0; k < S; ++k) {
     M_Apm[k] *= scale;
     const int64_t kg = (int64_t)(a->p.n_discard + period) * S + k;
     H_T[k] = a->p.dt_override > 0
-                 ? a->p.mu0Hmax
-                 : a->p.mu0Hmax * std::cos(2.0 * 3.14159265358979323846 * (double)kg / (double)S);
+                 ? hm
+                 : hm * std::cos(2.0 * 3.14159265358979323846 * (double)kg / (double)S);
   }
   return MH_OK;
 }

@@ -100,14 +100,15 @@ def test_dipolar_field_fp32(ctx, lib, n):
         assert err < 1e-5, err
 
 
-@pytest.mark.parametrize("n,prec", [(100, 0), (300, 0), (2000, 1), (60, 1)])
-def test_single_step_parity(ctx, lib, n, prec):
+@pytest.mark.parametrize("n,prec,nrep", [(100, 0, 2), (300, 0, 2), (2000, 1, 2), (60, 1, 2),
+                                         (1500, 1, 3), (700, 1, 4), (333, 1, 5)])
+def test_single_step_parity(ctx, lib, n, prec, nrep):
     R_l = 80e-9 * (n / 100) ** (1 / 3)
     pos = W.place_random(n, R_l, 12e-9, 500 + n)
     axes = W.axes_random_3d(n, 600 + n)
     pg, pk = _params(lib, prec)
     a = lib.Assembly(ctx, pos, axes, pg)
-    nrep, seed = 2, 4242
+    seed = 4242
     m_in = np.stack([_rand_moments(n, 10 + r) for r in range(nrep)])
     for k in (0, 437, 1000, 2999):
         diag = a.debug_steps(nrep, seed, k, k + 1, m_in.reshape(-1, 3))
@@ -150,6 +151,28 @@ def test_trajectory_config1_fp64(ctx, lib):
     assert np.abs(H - ref.H).max() < 1e-15
     assert abs(res["area"] - ref.area) < 1e-9 * max(abs(ref.area), 1.0)
     assert abs(res["sar"] - ref.sar) < 1e-9 * max(abs(ref.sar), 1.0)
+
+
+def test_per_replica_amplitudes_fp64(ctx, lib):
+    """Replicas at different field amplitudes (Sec. III.2.b sweeps): replica r follows
+    the oracle run at its amplitude with Philox stream r."""
+    n = 60
+    pos = W.place_random(n, 70e-9, 12e-9, 71)
+    axes = W.axes_random_3d(n, 72)
+    amps = [0.01, 0.02, 0.04]
+    pg, pk = _params(lib, lib.FP64, steps_per_period=100, n_periods=2, n_discard=1)
+    a = lib.Assembly(ctx, pos, axes, pg)
+    a.set_replica_fields(amps)
+    a.run(3, seed=99)
+    a.sync()
+    areas = a.replica_areas()
+    for r, h in enumerate(amps):
+        pk.mu0Hmax = h
+        ref = kmc.simulate(pos, axes, pk, seed=99, stream=r)
+        assert np.abs(a.moments(r) - ref.m_final).max() < 1e-9
+        assert abs(areas[r] - ref.area) < 1e-9 * max(1.0, abs(ref.area))
+        H, M = a.loop(r, 0)
+        assert np.abs(H - ref.H).max() < 1e-15
 
 
 def test_invalid_inputs_rejected(ctx, lib):
