@@ -45,7 +45,7 @@ struct SysDesc {
 struct WMArgs {
   const __bf16* whi;
   const __bf16* wlo;
-  __bf16* mhi;     // M^T hi: Rp x Kp
+  __bf16* mhi;     // M^T hi: Rp x Kp, fragment-major (see mt_offset in mh_wm.hip)
   __bf16* mlo;     // M^T lo
   float* bt;       // B^T: Rp x Mp (reduced dipolar sums)
   int Mp, Kp, Rp;

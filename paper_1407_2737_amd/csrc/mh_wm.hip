@@ -36,6 +36,18 @@ constexpr int WM_LD = WM_BK + 8;
 
 __device__ __forceinline__ __bf16 bf16_rn(float x) { return (__bf16)x; }
 
+// M^T is stored fragment-major: for replica tile r/32 and k-stage k/64, the 32 x 64
+// block is laid out as [sub][lane][8] with lane = 32 * (kk / 32) + r % 32,
+// sub = (kk % 32) / 8 (kk = k % 64), so the fragment load of one substep by a wave is
+// one contiguous 1 KB read.
+__device__ __forceinline__ size_t mt_offset(int r, int k, int Kp) {
+  const int rt = r >> 5, rr = r & 31;
+  const int kb = k >> 6, kk = k & 63;
+  const int lane = ((kk >> 5) << 5) + rr;
+  const int sub = (kk & 31) >> 3;
+  return ((((size_t)rt * (Kp >> 6) + kb) * 4 + sub) * 64 + lane) * 8 + (kk & 7);
+}
+
 // Builds W_hi, W_lo (Mp x Kp bf16, zero padded) from positions in units of d.
 __global__ void k_wm_build(const D4* __restrict__ pos, int n, __bf16* __restrict__ whi,
                            __bf16* __restrict__ wlo, int Mp, int Kp) {
@@ -77,13 +89,15 @@ __global__ __launch_bounds__(256) void k_wm_gemm(WMArgs g) {
   }
   const int wrow0 = rt * WM_BN;           // first W row (output column) of the block
   const int rep0 = ct * WM_BM + w * 64;   // first replica (output row) of this wave
-  // M^T fragment sources of this lane: two 32-replica tiles, lane's replica row,
-  // k = k0 + (lane/32)*32 + sub*8 + t
+  // M^T fragment sources of this lane (fragment-major layout, see mt_offset): for
+  // replica tile t the fragment of k-stage kb, substep s is 8 bf16 at
+  // (((tile * nkb + kb) * 4 + s) * 64 + lane) * 8
   const __bf16* ah[2];
   const __bf16* al[2];
+  const int nkb = g.Kp >> 6;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    const size_t off = (size_t)(rep0 + t * 32 + (lane & 31)) * g.Kp + (lane >> 5) * 32;
+    const size_t off = (size_t)((rep0 >> 5) + t) * nkb * 4 * 64 * 8 + (size_t)lane * 8;
     ah[t] = g.mhi + off;
     al[t] = g.mlo + off;
   }
@@ -113,16 +127,18 @@ __global__ __launch_bounds__(256) void k_wm_gemm(WMArgs g) {
     *reinterpret_cast<uint4*>(&Ws[buf][1][wr + 32][wk]) = w4;                    \
     *reinterpret_cast<uint4*>(&Ws[buf][1][wr + 64][wk]) = w5;                    \
   } while (0)
-  bf16x8 an[2][2][4];  // next stage M^T fragments [tile][hi/lo][sub]
-  auto load_a = [&](int k0) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        an[t][0][s] = *reinterpret_cast<const bf16x8*>(ah[t] + k0 + s * 8);
-        an[t][1][s] = *reinterpret_cast<const bf16x8*>(al[t] + k0 + s * 8);
-      }
-  };
+  // M^T fragments are prefetched two stages ahead through three register sets
+  // [tile][hi/lo][sub]; the stage loop is unrolled by three so each set has a fixed role
+  bf16x8 A0[2][2][4], A1[2][2][4], A2[2][2][4];
+#define MH_LOAD_A(A, k0)                                                              \
+  do {                                                                               \
+    _Pragma("unroll") for (int t = 0; t < 2; ++t) {                                  \
+      _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                \
+        A[t][0][s] = *reinterpret_cast<const bf16x8*>(ah[t] + ((k0) >> 6) * 2048 + s * 512); \
+        A[t][1][s] = *reinterpret_cast<const bf16x8*>(al[t] + ((k0) >> 6) * 2048 + s * 512); \
+      }                                                                              \
+    }                                                                                \
+  } while (0)
   f32x16 acc[2][3];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -132,62 +148,53 @@ __global__ __launch_bounds__(256) void k_wm_gemm(WMArgs g) {
       for (int e = 0; e < 16; ++e) acc[t][u][e] = 0.f;
 
   const int nst = g.Kp / WM_BK;
+  // one k-stage: issue the W loads of stage st+1 and the M^T loads of stage st+2, run
+  // the 72 MFMAs of stage st from LDS buffer st&1 and the registers AC, then store W of
+  // stage st+1 into the other LDS buffer
+#define MH_STAGE(AC, AN, st)                                                          \
+  do {                                                                               \
+    const int cur_ = (st) & 1;                                                       \
+    if ((st) + 1 < nst) MH_LOAD_W(((st) + 1) * WM_BK);                               \
+    if ((st) + 2 < nst) MH_LOAD_A(AN, ((st) + 2) * WM_BK);                           \
+    asm volatile("" ::: "memory");                                                   \
+    __builtin_amdgcn_sched_barrier(0);                                               \
+    _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                  \
+      bf16x8 bh[3], bl[3];                                                           \
+      _Pragma("unroll") for (int u = 0; u < 3; ++u) {                                \
+        const int r = u * 32 + (lane & 31);                                          \
+        const int kk = (lane >> 5) * 32 + s * 8;                                     \
+        bh[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur_][0][r][kk]);               \
+        bl[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur_][1][r][kk]);               \
+      }                                                                              \
+      _Pragma("unroll") for (int u = 0; u < 3; ++u) _Pragma("unroll") for (int t = 0; t < 2; ++t) \
+        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AC[t][0][s], bh[u], acc[t][u], 0, 0, 0); \
+      _Pragma("unroll") for (int u = 0; u < 3; ++u) _Pragma("unroll") for (int t = 0; t < 2; ++t) \
+        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AC[t][1][s], bh[u], acc[t][u], 0, 0, 0); \
+      _Pragma("unroll") for (int u = 0; u < 3; ++u) _Pragma("unroll") for (int t = 0; t < 2; ++t) \
+        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AC[t][0][s], bl[u], acc[t][u], 0, 0, 0); \
+    }                                                                                \
+    asm volatile("" ::: "memory");                                                   \
+    __builtin_amdgcn_sched_barrier(0);                                               \
+    if ((st) + 1 < nst) {                                                            \
+      MH_STORE_W(cur_ ^ 1);                                                          \
+      __syncthreads();                                                               \
+    }                                                                                \
+  } while (0)
+
   MH_LOAD_W(0);
-  load_a(0);
+  MH_LOAD_A(A0, 0);
+  if (nst > 1) MH_LOAD_A(A1, WM_BK);
   MH_STORE_W(0);
   __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
-    bf16x8 ac[2][2][4];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) ac[t][h][s] = an[t][h][s];
-    if (st + 1 < nst) {
-      MH_LOAD_W((st + 1) * WM_BK);
-      load_a((st + 1) * WM_BK);
-    }
-    // keep the next stage's loads in flight across the MFMAs: no memory operation may
-    // move over this point, and the LDS stores of the next stage stay after them
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      bf16x8 bh[3], bl[3];
-#pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        const int r = u * 32 + (lane & 31);
-        const int kk = (lane >> 5) * 32 + s * 8;
-        bh[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][0][r][kk]);
-        bl[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][1][r][kk]);
-      }
-      // the three split products sweep all six accumulators in turn, so consecutive
-      // MFMAs never depend on each other
-#pragma unroll
-      for (int u = 0; u < 3; ++u)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[t][0][s], bh[u], acc[t][u], 0, 0, 0);
-#pragma unroll
-      for (int u = 0; u < 3; ++u)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[t][1][s], bh[u], acc[t][u], 0, 0, 0);
-#pragma unroll
-      for (int u = 0; u < 3; ++u)
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[t][0][s], bl[u], acc[t][u], 0, 0, 0);
-    }
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-    if (st + 1 < nst) {
-      MH_STORE_W(cur ^ 1);
-      __syncthreads();
-    }
+  // the three split products sweep all six accumulators in turn inside a stage, so
+  // consecutive MFMAs never depend on each other
+  for (int st = 0; st < nst; st += 3) {
+    MH_STAGE(A0, A2, st);
+    if (st + 1 < nst) MH_STAGE(A1, A0, st + 1);
+    if (st + 2 < nst) MH_STAGE(A2, A1, st + 2);
   }
+#undef MH_STAGE
+#undef MH_LOAD_A
 #undef MH_LOAD_W
 #undef MH_STORE_W
   // B^T[replica][W row]: lane holds column wrow0 + u*32 + lane%32 of rows
@@ -212,8 +219,9 @@ __device__ __forceinline__ void store_split(const WMArgs& g, int r, int i, doubl
   for (int c = 0; c < 3; ++c) {
     const __bf16 h = bf16_rn((float)m[c]);
     const __bf16 l = bf16_rn((float)(m[c] - (double)(float)h));
-    g.mhi[(size_t)r * g.Kp + 3 * i + c] = h;
-    g.mlo[(size_t)r * g.Kp + 3 * i + c] = l;
+    const size_t o = mt_offset(r, 3 * i + c, g.Kp);
+    g.mhi[o] = h;
+    g.mlo[o] = l;
   }
 }
 
