@@ -1,0 +1,73 @@
+// Host build of the device-side step logic (Philox, Stoner-Wohlfarth extrema and fall,
+// per-particle update) so that the CPU test suite can compare it with the oracle.
+// Test infrastructure only: the GPU library is built from the same header by hipcc.
+#include <cmath>
+#include <cstdint>
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define HIP_INCLUDE_HIP_HIP_RUNTIME_H
+static inline uint64_t __umul64hi(uint64_t a, uint64_t b) {
+  return (uint64_t)(((__uint128_t)a * b) >> 64);
+}
+static inline void host_sincosf(float t, float* s, float* c) {
+  *s = std::sin(t);
+  *c = std::cos(t);
+}
+#define __sincosf host_sincosf
+using std::fabs;
+using std::fmax;
+#include "../../paper_1407_2737_amd/csrc/mh_device.hpp"
+
+extern "C" {
+
+void dl_philox(uint64_t seed, uint64_t stream, int64_t nblk, const uint64_t* ctr, uint64_t* out) {
+  for (int64_t b = 0; b < nblk; ++b) {
+    uint64_t c0 = ctr[4 * b], c1 = ctr[4 * b + 1], c2 = ctr[4 * b + 2], c3 = ctr[4 * b + 3];
+    mh::philox4x64_10(c0, c1, c2, c3, seed, stream);
+    out[4 * b] = c0;
+    out[4 * b + 1] = c1;
+    out[4 * b + 2] = c2;
+    out[4 * b + 3] = c3;
+  }
+}
+
+void dl_sw(int64_t n, const double* hx, const double* hy, const double* th0, double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    const mh::SWState r = mh::sw_fall(hx[i], hy[i], th0[i]);
+    double* o = out + 6 * i;
+    o[0] = r.th_c;
+    o[1] = r.e_c;
+    o[2] = r.th_o;
+    o[3] = r.e_o;
+    o[4] = r.e3;
+    o[5] = r.two ? 1.0 : 0.0;
+  }
+}
+
+// B, n, m: n x 3; out: n x 6 (new moment, P, jump, two)
+void dl_update(int64_t n, const double* B, const double* ax, const double* m, double BK,
+               double beta, double nu0dt, int prob_form, int thermal, uint64_t seed,
+               uint64_t stream, int64_t k, double* out) {
+  mh::NPParams p;
+  p.BK = BK;
+  p.BK_inv = 1.0 / BK;
+  p.beta = beta;
+  p.nu0dt = nu0dt;
+  p.prob_form = prob_form;
+  p.thermal = thermal;
+  p.aniso = 1;
+  for (int64_t i = 0; i < n; ++i) {
+    const mh::NPResult r =
+        mh::np_update(p, B[3 * i], B[3 * i + 1], B[3 * i + 2], ax[3 * i], ax[3 * i + 1],
+                      ax[3 * i + 2], m[3 * i], m[3 * i + 1], m[3 * i + 2], seed, stream, i, k);
+    double* o = out + 6 * i;
+    o[0] = r.mx;
+    o[1] = r.my;
+    o[2] = r.mz;
+    o[3] = r.P;
+    o[4] = r.jump;
+    o[5] = r.two;
+  }
+}
+}

@@ -1,0 +1,101 @@
+"""The device-side step logic (csrc/mh_device.hpp), compiled for the host, against the
+oracle: Philox words, Stoner-Wohlfarth extrema and basins (Eq. 2, steps iv-v), and the
+whole per-particle update with its Eq. 5 draw (steps iii-vii). Runs without a GPU, so
+the CPU suite checks the kernels' arithmetic; the GPU parity tests check the same
+functions as compiled for gfx950."""
+import ctypes as C
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import kmc, philox, sw
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hostshim", "device_logic.cpp")
+
+
+@pytest.fixture(scope="module")
+def dl():
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    d = tempfile.mkdtemp()
+    so = os.path.join(d, "device_logic.so")
+    r = subprocess.run([cxx, "-O2", "-std=c++17", "-shared", "-fPIC", "-I/opt/rocm/include", SRC,
+                        "-o", so], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    L = C.CDLL(so)
+    dp = C.POINTER(C.c_double)
+    u64p = C.POINTER(C.c_uint64)
+    L.dl_philox.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, u64p, u64p]
+    L.dl_sw.argtypes = [C.c_int64, dp, dp, dp, dp]
+    L.dl_update.argtypes = [C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
+                            C.c_int, C.c_uint64, C.c_uint64, C.c_int64, dp]
+    return L
+
+
+def _p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def test_philox_words(dl):
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 2**63, size=(300, 4), dtype=np.int64).astype(np.uint64)
+    out = np.empty_like(ctr)
+    p = C.POINTER(C.c_uint64)
+    dl.dl_philox(2**63 + 9, 77, ctr.shape[0], ctr.ctypes.data_as(p), out.ctypes.data_as(p))
+    assert np.array_equal(out, philox.raw_words(2**63 + 9, 77, ctr))
+
+
+def test_sw_fall_matches_oracle(dl):
+    rng = np.random.default_rng(6)
+    n = 30000
+    h = rng.uniform(0, 2.0, n) ** 1.5
+    phi = rng.uniform(0, np.pi, n)
+    hx, hy = h * np.cos(phi), h * np.sin(phi)
+    hx[:300] = rng.uniform(-1.5, 1.5, 300)
+    hy[:300] = 0.0
+    hx[300:600] = 0.0
+    hy[300:600] = rng.uniform(0, 1.5, 300)
+    # near the astroid: close min/max pairs
+    psi = rng.uniform(0.05, np.pi / 2 - 0.05, 400)
+    hsw = (np.cos(psi) ** (2 / 3) + np.sin(psi) ** (2 / 3)) ** -1.5
+    hh = hsw * (1 - 10 ** rng.uniform(-9, -3, 400))
+    hx[600:1000], hy[600:1000] = hh * np.cos(psi), hh * np.sin(psi)
+    th0 = rng.uniform(-np.pi, np.pi, n)
+    out = np.empty((n, 6))
+    dl.dl_sw(n, _p(hx), _p(hy), _p(th0), _p(out))
+    th, mn, cnt = sw.stationary_points(hx, hy)
+    tc, ec, to, eo, e3, two = sw.classify(th0, th, mn, cnt, hx, hy)
+    assert np.array_equal(out[:, 5] == 1.0, two)
+    dc = np.abs(np.angle(np.exp(1j * (out[:, 0] - tc))))
+    assert dc.max() < 1e-9, dc.max()
+    assert np.abs(out[:, 1] - ec).max() < 1e-12
+    assert np.abs(out[two, 4] - e3[two]).max() < 1e-12
+
+
+@pytest.mark.parametrize("prob_form", [0, 1])
+def test_update_matches_oracle_step(dl, prob_form):
+    rng = np.random.default_rng(7 + prob_form)
+    n = 4000
+    p = kmc.Params(Ms=4e5, Keff=1.3e4, d=12e-9, T=300.0, mu0Hmax=0.02, interactions=0,
+                   prob_form=prob_form)
+    dv = kmc.derived(p)
+    axes = rng.normal(size=(n, 3))
+    axes /= np.linalg.norm(axes, axis=1, keepdims=True)
+    m = rng.normal(size=(n, 3))
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    B = rng.normal(size=(n, 3)) * rng.uniform(0, 0.08, size=(n, 1))
+    k = 1234
+    m_new, info = kmc.step(np.zeros((n, 3)), axes, m, k, p, 4321, 3, B_override=B)
+    out = np.empty((n, 6))
+    dl.dl_update(n, _p(B), _p(axes), _p(m), dv["BK"], dv["beta"], dv["nu0dt"], prob_form, 1,
+                 4321, 3, k, _p(out))
+    assert np.array_equal(out[:, 5] == 1.0, info.two)
+    assert np.array_equal(out[:, 4] == 1.0, info.jump)
+    assert np.abs(out[:, 3] - info.P).max() < 1e-12
+    assert np.abs(out[:, :3] - m_new).max() < 1e-9
