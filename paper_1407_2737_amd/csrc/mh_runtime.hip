@@ -34,6 +34,7 @@ hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st);
 int wm_tile_rows();
 int wm_tile_reps();
 int wm_tile_k();
+int wm_ksplit();
 hipError_t launch_wm_build(const D4* pos, int n, __bf16* whi, __bf16* wlo, int Mp, int Kp,
                            hipStream_t st);
 hipError_t launch_wm_gemm(const WMArgs& g, hipStream_t st);
@@ -285,7 +286,7 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
         return MH_EDEVICE;
       a->Rp = Rp;
     }
-    if ((e = a->bt.ensure(sizeof(float) * (size_t)Rp * a->Mp))) return e;
+    if ((e = a->bt.ensure(sizeof(float) * (size_t)wm_ksplit() * Rp * a->Mp))) return e;
   }
   a->R = R;
   a->seed = seed;
@@ -1066,10 +1067,10 @@ size_t request_bytes(int64_t n, const mh_params& p, int64_t R, int64_t maxR) {
   size_t b = (size_t)R * n * (2 * 32 + 2 * 16 + 16 + 32) + (size_t)R * rows * (nt + 1) * 8;
   b += (size_t)n * (32 + 16 + 32) + (size_t)maxR * 8 + 4096;
   if (p.precision == MH_BF16X3_WM) {
-    const int64_t rq = 8 * 96;
-    const int64_t Mp = (3 * n + rq - 1) / rq * rq, Kp = (3 * n + 63) / 64 * 64;
+    const int64_t rq = 8 * 192;
+    const int64_t Mp = (3 * n + rq - 1) / rq * rq, Kp = (3 * n + 127) / 128 * 128;
     const int64_t Rp = (R + 255) / 256 * 256;
-    b += (size_t)Mp * Kp * 4 + (size_t)Rp * Kp * 4 + (size_t)Rp * Mp * 4;
+    b += (size_t)Mp * Kp * 4 + (size_t)Rp * Kp * 4 + (size_t)2 * Rp * Mp * 4;
   }
   return b;
 }

@@ -13,12 +13,14 @@
 // contiguous), and it writes B^T (replica-major), which the per-particle update then
 // reads contiguously.
 //
-// Tiling: block = 4 waves, tile = 256 replicas x 96 matrix rows, k-stage 64. The 96
-// W rows of a stage (hi and lo) are staged through LDS (double buffered, rows padded
-// to 72 bf16 so that 16-byte fragment reads do not conflict); each wave owns 64
-// replicas and loads its M^T fragments straight from global memory, one stage ahead.
-// Blocks are mapped so that the two replica tiles of a W row tile run on the same XCD
-// (blockIdx mod 8), which fetches every W slab from HBM once per step.
+// Tiling: block = 8 waves, tile = 256 replicas x 192 matrix rows over half of k (two k
+// splits whose partial products the update kernel adds in fixed order), k-stage 64.
+// The 192 W rows of a stage (hi and lo) are staged through LDS (double buffered, rows
+// padded to 72 bf16 so that 16-byte fragment reads do not conflict); each wave owns 32
+// replicas x 192 rows (six 32x32 accumulators) and loads its M^T fragments straight
+// from global memory, one stage ahead. The tile size sets the operand traffic from L2
+// per step: W once per replica tile (2x), M^T once per W row tile (3N/192 x). An XCD
+// (block index mod 8) owns whole W row tiles, so each W slab comes from HBM once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -30,8 +32,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int WM_BM = 256;  // replicas per block
-constexpr int WM_BN = 96;   // W rows per block
+constexpr int WM_BN = 192;  // W rows per block
 constexpr int WM_BK = 64;   // k per stage
+constexpr int WM_SK = 2;    // k splits (partial products summed by the update)
 constexpr int WM_LD = WM_BK + 8;
 
 __device__ __forceinline__ __bf16 bf16_rn(float x) { return (__bf16)x; }
@@ -72,42 +75,41 @@ __global__ void k_wm_build(const D4* __restrict__ pos, int n, __bf16* __restrict
 }
 
 
-__global__ __launch_bounds__(256) void k_wm_gemm(WMArgs g) {
+__global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
   __shared__ __attribute__((aligned(16))) __bf16 Ws[2][2][WM_BN][WM_LD];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  // block -> (W row tile, replica tile); XCD-aware when the shape allows it
-  int rt, ct;
-  const int nb = g.n_rtiles * g.n_ctiles;
+  // block -> (W row tile, k split, replica tile); XCD-aware when the shape allows it:
+  // an XCD (block index mod 8) owns whole W row tiles, both k splits and both replica
+  // tiles, so each W slab is fetched from HBM once per step into that XCD's L2
+  int rt, ks, ct;
+  const int nb = g.n_rtiles * g.n_ctiles * WM_SK;
   if (g.n_ctiles == 2 && (g.n_rtiles & 7) == 0 && nb == (int)gridDim.x) {
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    rt = xcd * (g.n_rtiles >> 3) + (slot >> 1);
+    rt = xcd * (g.n_rtiles >> 3) + (slot >> 2);
+    ks = (slot >> 1) & 1;
     ct = slot & 1;
   } else {
-    rt = blockIdx.x / g.n_ctiles;
-    ct = blockIdx.x - rt * g.n_ctiles;
+    ct = blockIdx.x % g.n_ctiles;
+    ks = (blockIdx.x / g.n_ctiles) % WM_SK;
+    rt = blockIdx.x / (g.n_ctiles * WM_SK);
   }
   const int wrow0 = rt * WM_BN;           // first W row (output column) of the block
-  const int rep0 = ct * WM_BM + w * 64;   // first replica (output row) of this wave
-  // M^T fragment sources of this lane (fragment-major layout, see mt_offset): for
-  // replica tile t the fragment of k-stage kb, substep s is 8 bf16 at
-  // (((tile * nkb + kb) * 4 + s) * 64 + lane) * 8
-  const __bf16* ah[2];
-  const __bf16* al[2];
+  const int rep0 = ct * WM_BM + w * 32;   // the wave's 32 replicas (output rows)
+  const int kbeg = ks * (g.Kp / WM_SK);
+  // M^T fragments of the wave's 32-replica tile (fragment-major layout, see mt_offset):
+  // k-stage kb, substep s at ((tile * nkb + kb) * 4 + s) * 64 * 8 + lane * 8
   const int nkb = g.Kp >> 6;
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const size_t off = (size_t)((rep0 >> 5) + t) * nkb * 4 * 64 * 8 + (size_t)lane * 8;
-    ah[t] = g.mhi + off;
-    al[t] = g.mlo + off;
-  }
-  // W stage loads: 96 rows x 8 chunks of 8 bf16, hi and lo = 1536 chunks, 6 per thread
-  // (chunk c = tid + 256 q: rows 0..95 of hi for q < 3, of lo for q >= 3). The six
-  // chunks are held in named registers; a register array here would be moved to LDS.
+  const size_t aoff = (size_t)(rep0 >> 5) * nkb * 4 * 64 * 8 + (size_t)lane * 8;
+  const __bf16* ah = g.mhi + aoff;
+  const __bf16* al = g.mlo + aoff;
+  // W stage loads: 192 rows x 8 chunks of 8 bf16, hi and lo = 3072 chunks, 6 per thread
+  // (rows tid/8 + 64 q for q = 0, 1, 2 of hi, then of lo), held in named registers (a
+  // register array here would be moved to LDS)
   const int wr = tid >> 3, wk = (tid & 7) * 8;
   const __bf16* wsrc_h = g.whi + (size_t)(wrow0 + wr) * g.Kp + wk;
   const __bf16* wsrc_l = g.wlo + (size_t)(wrow0 + wr) * g.Kp + wk;
-  const size_t wstep = (size_t)32 * g.Kp;  // 32 rows further for the next q
+  const size_t wstep = (size_t)64 * g.Kp;  // 64 rows further for the next q
   uint4 w0, w1, w2, w3, w4, w5;
 #define MH_LOAD_W(k0)                                                             \
   do {                                                                           \
@@ -121,94 +123,88 @@ __global__ __launch_bounds__(256) void k_wm_gemm(WMArgs g) {
 #define MH_STORE_W(buf)                                                          \
   do {                                                                           \
     *reinterpret_cast<uint4*>(&Ws[buf][0][wr][wk]) = w0;                         \
-    *reinterpret_cast<uint4*>(&Ws[buf][0][wr + 32][wk]) = w1;                    \
-    *reinterpret_cast<uint4*>(&Ws[buf][0][wr + 64][wk]) = w2;                    \
+    *reinterpret_cast<uint4*>(&Ws[buf][0][wr + 64][wk]) = w1;                    \
+    *reinterpret_cast<uint4*>(&Ws[buf][0][wr + 128][wk]) = w2;                   \
     *reinterpret_cast<uint4*>(&Ws[buf][1][wr][wk]) = w3;                         \
-    *reinterpret_cast<uint4*>(&Ws[buf][1][wr + 32][wk]) = w4;                    \
-    *reinterpret_cast<uint4*>(&Ws[buf][1][wr + 64][wk]) = w5;                    \
+    *reinterpret_cast<uint4*>(&Ws[buf][1][wr + 64][wk]) = w4;                    \
+    *reinterpret_cast<uint4*>(&Ws[buf][1][wr + 128][wk]) = w5;                   \
   } while (0)
-  // M^T fragments are prefetched two stages ahead through three register sets
-  // [tile][hi/lo][sub]; the stage loop is unrolled by three so each set has a fixed role
-  bf16x8 A0[2][2][4], A1[2][2][4], A2[2][2][4];
-#define MH_LOAD_A(A, k0)                                                              \
-  do {                                                                               \
-    _Pragma("unroll") for (int t = 0; t < 2; ++t) {                                  \
-      _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                \
-        A[t][0][s] = *reinterpret_cast<const bf16x8*>(ah[t] + ((k0) >> 6) * 2048 + s * 512); \
-        A[t][1][s] = *reinterpret_cast<const bf16x8*>(al[t] + ((k0) >> 6) * 2048 + s * 512); \
-      }                                                                              \
-    }                                                                                \
+  bf16x8 an[2][4];  // next stage M^T fragments [hi/lo][sub]
+#define MH_LOAD_A(k0)                                                            \
+  do {                                                                           \
+    _Pragma("unroll") for (int s = 0; s < 4; ++s) {                              \
+      an[0][s] = *reinterpret_cast<const bf16x8*>(ah + ((k0) >> 6) * 2048 + s * 512); \
+      an[1][s] = *reinterpret_cast<const bf16x8*>(al + ((k0) >> 6) * 2048 + s * 512); \
+    }                                                                            \
   } while (0)
-  f32x16 acc[2][3];
+  f32x16 acc[6];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int u = 0; u < 6; ++u)
 #pragma unroll
-    for (int u = 0; u < 3; ++u)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc[t][u][e] = 0.f;
+    for (int e = 0; e < 16; ++e) acc[u][e] = 0.f;
 
-  const int nst = g.Kp / WM_BK;
-  // one k-stage: issue the W loads of stage st+1 and the M^T loads of stage st+2, run
-  // the 72 MFMAs of stage st from LDS buffer st&1 and the registers AC, then store W of
-  // stage st+1 into the other LDS buffer
-#define MH_STAGE(AC, AN, st)                                                          \
-  do {                                                                               \
-    const int cur_ = (st) & 1;                                                       \
-    if ((st) + 1 < nst) MH_LOAD_W(((st) + 1) * WM_BK);                               \
-    if ((st) + 2 < nst) MH_LOAD_A(AN, ((st) + 2) * WM_BK);                           \
-    asm volatile("" ::: "memory");                                                   \
-    __builtin_amdgcn_sched_barrier(0);                                               \
-    _Pragma("unroll") for (int s = 0; s < 4; ++s) {                                  \
-      bf16x8 bh[3], bl[3];                                                           \
-      _Pragma("unroll") for (int u = 0; u < 3; ++u) {                                \
-        const int r = u * 32 + (lane & 31);                                          \
-        const int kk = (lane >> 5) * 32 + s * 8;                                     \
-        bh[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur_][0][r][kk]);               \
-        bl[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur_][1][r][kk]);               \
-      }                                                                              \
-      _Pragma("unroll") for (int u = 0; u < 3; ++u) _Pragma("unroll") for (int t = 0; t < 2; ++t) \
-        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AC[t][0][s], bh[u], acc[t][u], 0, 0, 0); \
-      _Pragma("unroll") for (int u = 0; u < 3; ++u) _Pragma("unroll") for (int t = 0; t < 2; ++t) \
-        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AC[t][1][s], bh[u], acc[t][u], 0, 0, 0); \
-      _Pragma("unroll") for (int u = 0; u < 3; ++u) _Pragma("unroll") for (int t = 0; t < 2; ++t) \
-        acc[t][u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(AC[t][0][s], bl[u], acc[t][u], 0, 0, 0); \
-    }                                                                                \
-    asm volatile("" ::: "memory");                                                   \
-    __builtin_amdgcn_sched_barrier(0);                                               \
-    if ((st) + 1 < nst) {                                                            \
-      MH_STORE_W(cur_ ^ 1);                                                          \
-      __syncthreads();                                                               \
-    }                                                                                \
-  } while (0)
-
-  MH_LOAD_W(0);
-  MH_LOAD_A(A0, 0);
-  if (nst > 1) MH_LOAD_A(A1, WM_BK);
+  const int nst = g.Kp / WM_SK / WM_BK;
+  MH_LOAD_W(kbeg);
+  MH_LOAD_A(kbeg);
   MH_STORE_W(0);
   __syncthreads();
-  // the three split products sweep all six accumulators in turn inside a stage, so
-  // consecutive MFMAs never depend on each other
-  for (int st = 0; st < nst; st += 3) {
-    MH_STAGE(A0, A2, st);
-    if (st + 1 < nst) MH_STAGE(A1, A0, st + 1);
-    if (st + 2 < nst) MH_STAGE(A2, A1, st + 2);
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    bf16x8 ac[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) ac[h][s] = an[h][s];
+    if (st + 1 < nst) {
+      MH_LOAD_W(kbeg + (st + 1) * WM_BK);
+      MH_LOAD_A(kbeg + (st + 1) * WM_BK);
+    }
+    // keep the next stage's loads in flight across the MFMAs: no memory operation may
+    // move over this point, and the LDS stores of the next stage stay after them
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = (lane >> 5) * 32 + s * 8;
+      bf16x8 bh[6], bl[6];
+#pragma unroll
+      for (int u = 0; u < 6; ++u) {
+        bh[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][0][u * 32 + (lane & 31)][kk]);
+        bl[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][1][u * 32 + (lane & 31)][kk]);
+      }
+      // the three split products sweep the six accumulators in turn, so consecutive
+      // MFMAs never depend on each other
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bh[u], acc[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[1][s], bh[u], acc[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bl[u], acc[u], 0, 0, 0);
+    }
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    if (st + 1 < nst) {
+      MH_STORE_W(cur ^ 1);
+      __syncthreads();
+    }
   }
-#undef MH_STAGE
 #undef MH_LOAD_A
 #undef MH_LOAD_W
 #undef MH_STORE_W
-  // B^T[replica][W row]: lane holds column wrow0 + u*32 + lane%32 of rows
-  // rep0 + t*32 + 8*(e/4) + 4*(lane/32) + e%4
+  // partial B^T of k split ks: lane holds column wrow0 + u*32 + lane%32 of rows
+  // rep0 + 8*(e/4) + 4*(lane/32) + e%4
+  float* bt = g.bt + (size_t)ks * g.Rp * g.Mp;
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int u = 0; u < 6; ++u)
 #pragma unroll
-    for (int u = 0; u < 3; ++u)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = rep0 + t * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        const int col = wrow0 + u * 32 + (lane & 31);
-        g.bt[(size_t)row * g.Mp + col] = acc[t][u][e];
-      }
+    for (int e = 0; e < 16; ++e) {
+      const int row = rep0 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      const int col = wrow0 + u * 32 + (lane & 31);
+      bt[(size_t)row * g.Mp + col] = acc[u][e];
+    }
 }
 
 // hi/lo split of the moments of replica r, particle i into M^T.
@@ -250,8 +246,16 @@ __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ s
   const int cur = (int)(k & 1);
   double mx = 0.0;
   if (i < s.n) {
-    const float* f = g.bt + (size_t)r * g.Mp + 3 * i;
-    mx = np_epilogue(s, i, k, cur, (double)f[0], (double)f[1], (double)f[2]);
+    // partial products of the k splits, added in fixed order
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll
+    for (int q = 0; q < WM_SK; ++q) {
+      const float* f = g.bt + (size_t)q * g.Rp * g.Mp + (size_t)r * g.Mp + 3 * i;
+      fx += (double)f[0];
+      fy += (double)f[1];
+      fz += (double)f[2];
+    }
+    mx = np_epilogue(s, i, k, cur, fx, fy, fz);
     if (!s.field_only) {
       const D4 m = s.m64[(int64_t)(cur ^ 1) * s.stride + i];
       store_split(g, r, i, m.x, m.y, m.z);
@@ -273,7 +277,8 @@ __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ s
 // ---------------------------------------------------------------------------
 int wm_tile_rows() { return WM_BN; }
 int wm_tile_reps() { return WM_BM; }
-int wm_tile_k() { return WM_BK; }
+int wm_tile_k() { return WM_BK * WM_SK; }
+int wm_ksplit() { return WM_SK; }
 
 hipError_t launch_wm_build(const D4* pos, int n, __bf16* whi, __bf16* wlo, int Mp, int Kp,
                            hipStream_t st) {
@@ -283,7 +288,7 @@ hipError_t launch_wm_build(const D4* pos, int n, __bf16* whi, __bf16* wlo, int M
 }
 
 hipError_t launch_wm_gemm(const WMArgs& g, hipStream_t st) {
-  hipLaunchKernelGGL(k_wm_gemm, dim3(g.n_rtiles * g.n_ctiles), dim3(256), 0, st, g);
+  hipLaunchKernelGGL(k_wm_gemm, dim3(g.n_rtiles * g.n_ctiles * WM_SK), dim3(512), 0, st, g);
   return hipGetLastError();
 }
 
