@@ -87,3 +87,23 @@ def test_wm_sar_matches_fp64_path(ctx, lib):
     tol = max(0.01 * abs(s64["area"]), 2 * np.hypot(s64["area_se"], swm["area_se"]))
     print(f"area FP64 {s64['area']:.5g} +- {s64['area_se']:.2g}, W.M {swm['area']:.5g} +- {swm['area_se']:.2g}")
     assert abs(s64["area"] - swm["area"]) < tol
+
+
+def test_fp32_sar_matches_fp64_path(ctx, lib):
+    """Run level for the FP32 field form (replica groups of four, source parts):
+    the loop area over 64 replicas agrees with the FP64 path within max(1 %, 2 SE)."""
+    n = 1400
+    pos = W.place_random(n, 160e-9, 12e-9, 905)
+    axes = W.axes_random_3d(n * 64, 906).reshape(64, n, 3)
+    kw = _kw(steps_per_period=100, n_periods=2, n_discard=1)
+    res = {}
+    for prec in (lib.FP64, lib.FP32_FIELD):
+        a = lib.Assembly(ctx, pos, axes, lib.Params.make(prec, **kw), n_axes_sets=64)
+        a.run(64, seed=2468)
+        a.sync()
+        res[prec] = a.sar()
+        a.close()
+    s64, s32 = res[lib.FP64], res[lib.FP32_FIELD]
+    tol = max(0.01 * abs(s64["area"]), 2 * np.hypot(s64["area_se"], s32["area_se"]))
+    print(f"area FP64 {s64['area']:.5g} +- {s64['area_se']:.2g}, FP32 {s32['area']:.5g} +- {s32['area_se']:.2g}")
+    assert abs(s64["area"] - s32["area"]) < tol
