@@ -64,113 +64,134 @@ __device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t stream,
 // ---------------------------------------------------------------------------
 // Stoner-Wohlfarth stationary points (reduced energy e = sin^2 - 2(hx cos + hy sin))
 // ---------------------------------------------------------------------------
+// Angles are carried as unit directions (sine, cosine). Brackets, Newton steps,
+// bisection and the basin test then need only products and signs: the sine of the
+// angle from p to q is cross(p, q), a step by dx rotates the pair, and the middle of
+// an arc narrower than pi is the normalised sum of its ends. No double-precision
+// sine, cosine or arctangent is evaluated on the update path.
+struct Dir {
+  double s, c;
+};
+
+__device__ __forceinline__ double cross(Dir p, Dir q) { return p.c * q.s - p.s * q.c; }
+
+// 1/sqrt(x) for x > 0: hardware estimate and two Newton refinements.
+__device__ __forceinline__ double rsqrt64(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  r = r * fma(-hx * r, r, 1.5);
+  return r * fma(-hx * r, r, 1.5);
+}
+
+__device__ __forceinline__ Dir unit(double s, double c) {
+  const double inv = rsqrt64(s * s + c * c);
+  return Dir{s * inv, c * inv};
+}
+
+// Direction of the in-plane projection (p, q) = (m.u, m.n) of a moment. A zero
+// projection takes the direction that atan2 gives signed zeros: angle 0 for q = +0,
+// pi for q = -0.
+__device__ __forceinline__ Dir dir_of(double p, double q) {
+  const double rho2 = p * p + q * q;
+  if (rho2 > 0.0) return unit(p, q);
+  return Dir{0.0, copysign(1.0, q)};
+}
+
 __device__ __forceinline__ double sw_energy(double s, double c, double hx, double hy) {
   return s * s - 2.0 * (hx * c + hy * s);
 }
 
-// g = e'/2 at t (returned) and dg/dt in gp.
-__device__ __forceinline__ double sw_g(double t, double hx, double hy, double& gp) {
-  double s, c;
-  sincos(t, &s, &c);
-  gp = (c * c - s * s) + hx * c + hy * s;
+// g = e'/2 (kDeriv = false) or g' = e''/2 (kDeriv = true) at direction (s, c), and its
+// derivative along the angle.
+template <bool kDeriv, typename T>
+__device__ __forceinline__ T sw_fn(T s, T c, T hx, T hy, T& d) {
+  if (kDeriv) {
+    d = T(-4) * s * c - hx * s + hy * c;
+    return (c * c - s * s) + hx * c + hy * s;
+  }
+  d = (c * c - s * s) + hx * c + hy * s;
   return s * c + hx * s - hy * c;
 }
 
-// g' = e''/2 at t (returned) and its derivative in gpp.
-__device__ __forceinline__ double sw_gp(double t, double hx, double hy, double& gpp) {
-  double s, c;
-  sincos(t, &s, &c);
-  gpp = -4.0 * s * c - hx * s + hy * c;
-  return (c * c - s * s) + hx * c + hy * s;
+// Double-precision reciprocal for Newton steps: hardware estimate and two Newton
+// refinements (the step only has to be accurate to a few ulp).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
 }
 
-// FP32 seed of a zero of g (kDeriv = false) or of g' (kDeriv = true) on (a, b), where the
-// function is negative at a iff a_neg: Newton kept inside the bracket, bisection when a
-// step leaves it. Accurate to the single-precision sine/cosine (about 1e-6).
+// FP32 seed of a zero of g / g' on the angle bracket (a, b), where the function is
+// negative at a iff a_neg: Newton kept inside the bracket, bisection when a step leaves
+// it, stopped once a step is below 1e-4 rad. Returns the angle and, in (so, co), its
+// sine and cosine with the last step applied to first order (about 1e-7 from the root),
+// which is where the double-precision polish starts.
 template <bool kDeriv>
-__device__ float seed_root(float a, float b, bool a_neg, float hx, float hy) {
+__device__ float seed_root(float a, float b, bool a_neg, float hx, float hy, float& so,
+                           float& co) {
   float x = 0.5f * (a + b);
-  for (int it = 0; it < 30; ++it) {
-    float s, c;
+  for (int it = 0;; ++it) {
+    float s, c, d;
     __sincosf(x, &s, &c);
-    float f, d;
-    if (kDeriv) {
-      f = (c * c - s * s) + hx * c + hy * s;
-      d = -4.f * s * c - hx * s + hy * c;
-    } else {
-      f = s * c + hx * s - hy * c;
-      d = (c * c - s * s) + hx * c + hy * s;
-    }
+    const float f = sw_fn<kDeriv>(s, c, hx, hy, d);
     if ((f < 0.f) == a_neg)
       a = x;
     else
       b = x;
-    const float dx = -f / d;
-    if (fabsf(dx) < 1e-6f) break;  // converged to single precision
+    const float dx = -f * __builtin_amdgcn_rcpf(d);
+    if (fabsf(dx) < 1e-4f) {
+      so = s + c * dx;
+      co = c - s * dx;
+      return x + dx;
+    }
+    if (it == 29) {
+      so = s;
+      co = c;
+      return x;
+    }
     float xn = x + dx;
     if (!(xn > a && xn < b)) xn = 0.5f * (a + b);
     x = xn;
   }
-  return x;
 }
 
-// FP64 zero of g / g' on the FP64 bracket (a, b), started from x0. Newton steps rotate
-// the pair (sin x, cos x) by the step with a short Taylor series once the step is below
-// 1e-3, so a converged polish costs one double-precision sincos. Returns the root and
-// its sine and cosine.
+// FP64 zero of g / g' on the arc (a, b) (counter-clockwise, narrower than pi), where the
+// function is negative at a iff a_neg, started from direction x. Newton steps below
+// 1e-3 rad rotate the direction by a short Taylor series of the step's sine and cosine;
+// a step that is larger or leaves the arc is replaced by bisection. Stops when the step
+// is below 2e-16 rad, when a step below 1e-12 no longer halves the previous one (the
+// iterate is inside the rounding band of the root, which is wide where g' is small),
+// or when the arc is below 4e-16.
 template <bool kDeriv>
-__device__ double polish_root(double a, double b, bool a_neg, double hx, double hy, double x0,
-                              double& s_out, double& c_out) {
-  double x = (x0 > a && x0 < b) ? x0 : 0.5 * (a + b);
-  double s, c;
-  sincos(x, &s, &c);
+__device__ Dir polish_root(Dir a, Dir b, bool a_neg, double hx, double hy, Dir x) {
+  if (!(cross(a, x) > 0.0 && cross(x, b) > 0.0)) x = unit(a.s + b.s, a.c + b.c);
+  double prev = 1.0;
   for (int it = 0; it < 200; ++it) {
-    double f, d;
-    if (kDeriv) {
-      f = (c * c - s * s) + hx * c + hy * s;
-      d = -4.0 * s * c - hx * s + hy * c;
-    } else {
-      f = s * c + hx * s - hy * c;
-      d = (c * c - s * s) + hx * c + hy * s;
-    }
+    double d;
+    const double f = sw_fn<kDeriv>(x.s, x.c, hx, hy, d);
     if (f == 0.0) break;
     if ((f < 0.0) == a_neg)
       a = x;
     else
       b = x;
-    const double dx = -f / d;
-    if (fabs(dx) <= 2e-16 * fmax(1.0, fabs(x))) break;  // converged: x is the root
-    double xn = x + dx;
-    if (!(xn > a && xn < b)) {  // bisect
-      xn = 0.5 * (a + b);
-      if (xn == a || xn == b) break;
-      x = xn;
-      sincos(x, &s, &c);
-      continue;
-    }
-    if (fabs(dx) < 1e-3) {
+    const double dx = -f * rcp64(d);
+    const double adx = fabs(dx);
+    if (adx <= 2e-16 || (adx < 1e-12 && adx > 0.5 * prev)) break;  // x is the root
+    prev = adx;
+    if (adx < 1e-3) {
       const double d2 = dx * dx;
       const double cd = 1.0 - d2 * (0.5 - d2 * (1.0 / 24.0 - d2 * (1.0 / 720.0)));
       const double sd = dx * (1.0 - d2 * (1.0 / 6.0 - d2 * (1.0 / 120.0 - d2 * (1.0 / 5040.0))));
-      const double cn = c * cd - s * sd;
-      s = s * cd + c * sd;
-      c = cn;
-    } else {
-      sincos(xn, &s, &c);
+      const Dir xn{x.s * cd + x.c * sd, x.c * cd - x.s * sd};
+      if (cross(a, xn) > 0.0 && cross(xn, b) > 0.0) {
+        x = xn;
+        continue;
+      }
     }
-    x = xn;
-    if (fabs(dx) <= 2e-16 * fmax(1.0, fabs(x)) || (b - a) <= 4e-16 * fmax(1.0, fabs(x))) break;
+    if (cross(a, b) <= 4e-16) break;
+    x = unit(a.s + b.s, a.c + b.c);
   }
-  s_out = s;
-  c_out = c;
   return x;
-}
-
-template <bool kDeriv>
-__device__ __forceinline__ double find_root(double a, double b, bool a_neg, double hx, double hy,
-                                            double& s, double& c) {
-  const float x0 = seed_root<kDeriv>((float)a, (float)b, a_neg, (float)hx, (float)hy);
-  return polish_root<kDeriv>(a, b, a_neg, hx, hy, (double)x0, s, c);
 }
 
 __device__ __forceinline__ double wrap_pi(double t) {
@@ -186,64 +207,58 @@ __device__ __forceinline__ bool astroid_bistable(double hx, double hy) {
 }
 
 struct SWState {
-  double th_c, e_c, th_o, e_o, e3;  // current/other minimum, lower maximum (units K V)
-  double s_c, c_c, s_o, c_o;        // sine and cosine of th_c and th_o
+  double e_c, e_o, e3;  // current/other minimum, lower maximum (units K V)
+  double s_c, c_c, s_o, c_o;  // directions of the current and the other minimum
   bool two;
 };
 
-// Step iv-v: stationary points for (hx, hy) with hy >= 0, and the basin of theta0.
-__device__ SWState sw_fall(double hx, double hy, double theta0) {
+// Step iv-v: stationary points for (hx, hy) with hy >= 0, and the basin of the moment at
+// angle theta0, given as its direction d0 = (sin theta0, cos theta0).
+__device__ SWState sw_fall(double hx, double hy, Dir d0) {
   SWState r;
   // ---- exact special cases (field along or across the axis) ----
   if (hy == 0.0) {
     const double e0 = -2.0 * hx, epi = 2.0 * hx;
+    bool to0;  // current minimum at theta = 0 (else pi)
     if (fabs(hx) < 1.0) {
-      const double tm = acos(-hx);  // maxima at +-tm, both at energy 1 + hx^2
-      const double at = fabs(theta0);
-      bool to0;
-      if (at < tm)
+      // maxima at +-tm with cos tm = -hx, both at energy 1 + hx^2; |theta0| < tm is
+      // cos theta0 > -hx since the cosine falls on [0, pi]. On a maximum: the lower
+      // minimum, then the nearer (equal here), then the smaller angle (0).
+      if (d0.c > -hx)
         to0 = true;
-      else if (at > tm)
+      else if (d0.c < -hx)
         to0 = false;
       else
-        to0 = (e0 < epi) || (e0 == epi);  // tie on a maximum: lower energy, then nearer, then
-                                          // the smaller angle (0)
+        to0 = e0 <= epi;
       r.two = true;
-      r.th_c = to0 ? 0.0 : kPi;
-      r.e_c = to0 ? e0 : epi;
-      r.th_o = to0 ? kPi : 0.0;
-      r.e_o = to0 ? epi : e0;
       r.e3 = 1.0 + hx * hx;
+      r.e_o = to0 ? epi : e0;
     } else {
+      to0 = hx > 0.0;
       r.two = false;
-      r.th_c = r.th_o = hx > 0.0 ? 0.0 : kPi;
-      r.e_c = r.e_o = hx > 0.0 ? e0 : epi;
       r.e3 = 0.0;
+      r.e_o = to0 ? e0 : epi;
     }
+    r.e_c = to0 ? e0 : epi;
     r.s_c = r.s_o = 0.0;
-    r.c_c = r.th_c == 0.0 ? 1.0 : -1.0;
-    r.c_o = r.th_o == 0.0 ? 1.0 : -1.0;
+    r.c_c = to0 ? 1.0 : -1.0;
+    r.c_o = r.two ? -r.c_c : r.c_c;
     return r;
   }
   if (hx == 0.0) {
     if (hy < 1.0) {
-      const double a = asin(hy);
-      const double em = -hy * hy;  // both minima
-      // basins: (-pi/2, pi/2) -> a ; (pi/2, 3pi/2) -> pi - a ; ties go to a
-      const double t = theta0;
-      const bool toa = (t > -kHalfPi && t < kHalfPi) || t == kHalfPi || t == -kHalfPi;
-      r.two = true;
-      r.th_c = toa ? a : kPi - a;
-      r.th_o = toa ? kPi - a : a;
-      r.e_c = r.e_o = em;
-      r.e3 = 1.0 - 2.0 * hy;
+      // minima at asin(hy) and pi - asin(hy), both at -hy^2; basins (-pi/2, pi/2) and
+      // (pi/2, 3pi/2), ties (cos theta0 = 0) to the first
+      const bool toa = d0.c >= 0.0;
       const double ca = sqrt((1.0 - hy) * (1.0 + hy));
+      r.two = true;
+      r.e_c = r.e_o = -hy * hy;
+      r.e3 = 1.0 - 2.0 * hy;
       r.s_c = r.s_o = hy;
       r.c_c = toa ? ca : -ca;
-      r.c_o = toa ? -ca : ca;
+      r.c_o = -r.c_c;
     } else {
       r.two = false;
-      r.th_c = r.th_o = kHalfPi;
       r.e_c = r.e_o = 1.0 - 2.0 * hy;
       r.e3 = 0.0;
       r.s_c = r.s_o = 1.0;
@@ -251,83 +266,92 @@ __device__ SWState sw_fall(double hx, double hy, double theta0) {
     }
     return r;
   }
-  // ---- general case: reflect into hx > 0 ----
+  // ---- general case: reflect into hx > 0 (theta -> pi - theta flips the cosine) ----
   const bool refl = hx < 0.0;
   const double ax = fabs(hx);
-  double s1, c1;
-  const double r1 = find_root<false>(0.0, kHalfPi, true, ax, hy, s1, c1);  // global minimum
-  const double e1 = sw_energy(s1, c1, ax, hy);
+  const float axf = (float)ax, hyf = (float)hy;
+  const float kPiF = (float)kPi, kHalfPiF = (float)kHalfPi;
+  const Dir east{0.0, 1.0}, north{1.0, 0.0}, west{0.0, -1.0};  // angles 0, pi/2, pi
+  float fs, fc;
+  seed_root<false>(0.f, kHalfPiF, true, axf, hyf, fs, fc);
+  const Dir d1 = polish_root<false>(east, north, true, ax, hy, unit(fs, fc));  // global min
+  const double e1 = sw_energy(d1.s, d1.c, ax, hy);
   bool two = false;
-  double r2a = 0.0, r2b = 0.0, e2a = 0.0, e2b = 0.0, s2 = 0.0, c2 = 0.0;
+  Dir d2a{0.0, 0.0}, d2b{0.0, 0.0};
+  double e2a = 0.0, e2b = 0.0;
   if (astroid_bistable(ax, hy)) {
-    // the zero t* of g' in (pi/2, pi) separates the saddle maximum and the metastable
-    // minimum; the single-precision t* is used when g < 0 there in double precision
-    double ts = (double)seed_root<true>((float)kHalfPi, (float)kPi, true, (float)ax, (float)hy);
-    if (!(ts > kHalfPi && ts < kPi)) ts = 0.5 * (kHalfPi + kPi);
-    double st, ct;
-    sincos(ts, &st, &ct);
-    if (!(st * ct + ax * st - hy * ct < 0.0)) ts = polish_root<true>(kHalfPi, kPi, true, ax, hy, ts, st, ct);
-    if (st * ct + ax * st - hy * ct < 0.0) {
+    // a direction between the saddle maximum and the metastable minimum in (pi/2, pi):
+    // the FP32 zero t* of g', kept when g < 0 there in double precision, else polished
+    float ts = seed_root<true>(kHalfPiF, kPiF, true, axf, hyf, fs, fc);
+    Dir dt = unit(fs, fc);
+    if (!(dt.s > 0.0 && dt.c < 0.0 && ts > kHalfPiF && ts < kPiF)) {
+      ts = 0.75f * kPiF;
+      dt = unit(1.0, -1.0);
+    }
+    double gt = dt.s * dt.c + ax * dt.s - hy * dt.c;
+    if (!(gt < 0.0)) {
+      dt = polish_root<true>(north, west, true, ax, hy, dt);
+      gt = dt.s * dt.c + ax * dt.s - hy * dt.c;
+      ts = atan2f((float)dt.s, (float)dt.c);
+    }
+    if (gt < 0.0) {
       two = true;
-      double sa, ca;
-      r2a = find_root<false>(kHalfPi, ts, false, ax, hy, sa, ca);  // saddle maximum
-      r2b = find_root<false>(ts, kPi, true, ax, hy, s2, c2);       // metastable minimum
-      e2a = sw_energy(sa, ca, ax, hy);
-      e2b = sw_energy(s2, c2, ax, hy);
+      seed_root<false>(kHalfPiF, ts, false, axf, hyf, fs, fc);
+      d2a = polish_root<false>(north, dt, false, ax, hy, unit(fs, fc));  // saddle maximum
+      seed_root<false>(ts, kPiF, true, axf, hyf, fs, fc);
+      d2b = polish_root<false>(dt, west, true, ax, hy, unit(fs, fc));  // metastable minimum
+      e2a = sw_energy(d2a.s, d2a.c, ax, hy);
+      e2b = sw_energy(d2b.s, d2b.c, ax, hy);
     }
   }
-  // back to the unreflected frame: theta = pi - theta_r flips the cosine
-  const double back1 = refl ? wrap_pi(kPi - r1) : r1;
-  r.s_c = s1;
-  r.c_c = refl ? -c1 : c1;
+  const Dir u1{d1.s, refl ? -d1.c : d1.c};  // unreflected directions
   if (!two) {
     r.two = false;
-    r.th_c = r.th_o = back1;
     r.e_c = r.e_o = e1;
     r.e3 = 0.0;
-    r.s_o = r.s_c;
-    r.c_o = r.c_c;
+    r.s_c = r.s_o = u1.s;
+    r.c_c = r.c_o = u1.c;
     return r;
   }
-  // basin of theta0. In the reflected frame the circle reads r1 (min) < r2a (max) <
-  // r2b (min) < r3 (max) < r1 + 2 pi, with r3 the global maximum in (pi, 3 pi / 2);
-  // r3 is only needed when the moment lies in that quadrant.
-  double y = refl ? (kPi - theta0) : theta0;
-  if (y >= 1.5 * kPi) y -= 2.0 * kPi;
-  if (y < -kHalfPi) y += 2.0 * kPi;
+  const Dir u2{d2b.s, refl ? -d2b.c : d2b.c};
+  // Basin of theta0. In the reflected frame (angle y, sine sr, cosine cr) the circle
+  // reads r1 (min) < r2a (max) < r2b (min) < r3 (max) < r1 + 2 pi with r1 in (0, pi/2),
+  // r2a and r2b in (pi/2, pi) and r3 in (pi, 3 pi/2):
+  //   cr >= 0           y in [-pi/2, pi/2], before r2a: minimum r1;
+  //   cr < 0, sr >= 0   y in (pi/2, pi]: before r2a iff sin(r2a - y) > 0;
+  //   cr < 0, sr < 0    y in (pi, 3 pi/2): before r3 iff g(y) > 0, as r3 is the only
+  //                     zero of g there and g(pi) = hy > 0 > -ax = g(3 pi/2).
+  // A zero sine or g puts the moment on a maximum (basin 0).
+  const Dir y{d0.s, refl ? -d0.c : d0.c};
   int basin;  // 1: r1, 2: r2b, 0: on a maximum
-  if (y < r2a)
+  if (y.c >= 0.0) {
     basin = 1;
-  else if (y == r2a)
-    basin = 0;
-  else if (y <= kPi)
-    basin = 2;
-  else {
-    double s3, c3;
-    const double r3 = find_root<false>(kPi, 1.5 * kPi, false, ax, hy, s3, c3);
-    basin = y < r3 ? 2 : (y > r3 ? 1 : 0);
+  } else if (y.s >= 0.0) {
+    const double x = cross(y, d2a);
+    basin = x > 0.0 ? 1 : (x < 0.0 ? 2 : 0);
+  } else {
+    const double gy = y.s * y.c + ax * y.s - hy * y.c;
+    basin = gy > 0.0 ? 2 : (gy < 0.0 ? 1 : 0);
   }
-  const double b2 = refl ? wrap_pi(kPi - r2b) : wrap_pi(r2b);
-  if (basin == 0) {
+  if (basin == 0) {  // on a maximum: the lower minimum, then the nearer, then the smaller angle
     if (e1 != e2b) {
       basin = e1 < e2b ? 1 : 2;
     } else {
-      const double d1 = fabs(wrap_pi(theta0 - back1)), d2 = fabs(wrap_pi(theta0 - b2));
-      basin = ((d1 < d2) || (d1 == d2 && back1 <= b2)) ? 1 : 2;
+      const double t0 = atan2(d0.s, d0.c);
+      const double t1 = atan2(u1.s, u1.c), t2 = atan2(u2.s, u2.c);
+      const double dd1 = fabs(wrap_pi(t0 - t1)), dd2 = fabs(wrap_pi(t0 - t2));
+      basin = ((dd1 < dd2) || (dd1 == dd2 && t1 <= t2)) ? 1 : 2;
     }
   }
   const bool to1 = basin == 1;
-  const double s2u = s2, c2u = refl ? -c2 : c2;
   r.two = true;
-  r.th_c = to1 ? back1 : b2;
   r.e_c = to1 ? e1 : e2b;
-  r.th_o = to1 ? b2 : back1;
   r.e_o = to1 ? e2b : e1;
   r.e3 = e2a;
-  r.s_c = to1 ? s1 : s2u;
-  r.c_c = to1 ? (refl ? -c1 : c1) : c2u;
-  r.s_o = to1 ? s2u : s1;
-  r.c_o = to1 ? c2u : (refl ? -c1 : c1);
+  r.s_c = to1 ? u1.s : u2.s;
+  r.c_c = to1 ? u1.c : u2.c;
+  r.s_o = to1 ? u2.s : u1.s;
+  r.c_o = to1 ? u2.c : u1.c;
   return r;
 }
 
@@ -374,14 +398,16 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
   // step iii: working plane (n, u2)
   const double bpar = Bx * nx + By * ny + Bz * nz;
   double px = Bx - bpar * nx, py = By - bpar * ny, pz = Bz - bpar * nz;
-  const double bp = sqrt(px * px + py * py + pz * pz);
-  const double bn = sqrt(Bx * Bx + By * By + Bz * Bz);
+  // |B_perp| > 1e-12 max(|B|, mu0 H_K), compared in squares
+  const double bp2 = px * px + py * py + pz * pz;
+  const double bn2 = Bx * Bx + By * By + Bz * Bz;
   double ux, uy, uz, hy;
-  if (bp > 1e-12 * fmax(bn, p.BK)) {
-    ux = px / bp;
-    uy = py / bp;
-    uz = pz / bp;
-    hy = bp * p.BK_inv;
+  if (bp2 > 1e-24 * fmax(bn2, p.BK * p.BK)) {
+    const double inv = rsqrt64(bp2);
+    ux = px * inv;
+    uy = py * inv;
+    uz = pz * inv;
+    hy = bp2 * inv * p.BK_inv;
   } else {
     hy = 0.0;
     const double mn = mx * nx + my * ny + mz * nz;
@@ -408,9 +434,9 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
     }
   }
   const double hx = bpar * p.BK_inv;
-  const double theta0 = atan2(mx * ux + my * uy + mz * uz, mx * nx + my * ny + mz * nz);
+  const Dir d0 = dir_of(mx * ux + my * uy + mz * uz, mx * nx + my * ny + mz * nz);
   // steps iv-v
-  const SWState sw = sw_fall(hx, hy, theta0);
+  const SWState sw = sw_fall(hx, hy, d0);
   double s = sw.s_c, c = sw.c_c;
   out.two = sw.two;
   // steps vi-vii

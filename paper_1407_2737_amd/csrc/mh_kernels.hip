@@ -439,11 +439,13 @@ __global__ void k_sw(const double* __restrict__ hx, const double* __restrict__ h
                      const double* __restrict__ th0, double* __restrict__ out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const SWState r = sw_fall(hx[i], hy[i], th0[i]);
+  Dir d;
+  sincos(th0[i], &d.s, &d.c);
+  const SWState r = sw_fall(hx[i], hy[i], d);
   double* o = out + 6 * i;
-  o[0] = r.th_c;
+  o[0] = atan2(r.s_c, r.c_c);
   o[1] = r.e_c;
-  o[2] = r.th_o;
+  o[2] = atan2(r.s_o, r.c_o);
   o[3] = r.e_o;
   o[4] = r.e3;
   o[5] = r.two ? 1.0 : 0.0;

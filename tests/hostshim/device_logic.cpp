@@ -15,8 +15,12 @@ static inline void host_sincosf(float t, float* s, float* c) {
   *c = std::cos(t);
 }
 #define __sincosf host_sincosf
+#define __builtin_amdgcn_rcpf(x) (1.0f / (x))
+#define __builtin_amdgcn_rcp(x) (1.0 / (x))
+#define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))
 using std::fabs;
 using std::fmax;
+using std::copysign;
 #include "../../paper_1407_2737_amd/csrc/mh_device.hpp"
 
 extern "C" {
@@ -34,11 +38,12 @@ void dl_philox(uint64_t seed, uint64_t stream, int64_t nblk, const uint64_t* ctr
 
 void dl_sw(int64_t n, const double* hx, const double* hy, const double* th0, double* out) {
   for (int64_t i = 0; i < n; ++i) {
-    const mh::SWState r = mh::sw_fall(hx[i], hy[i], th0[i]);
+    const mh::Dir d = {std::sin(th0[i]), std::cos(th0[i])};
+    const mh::SWState r = mh::sw_fall(hx[i], hy[i], d);
     double* o = out + 6 * i;
-    o[0] = r.th_c;
+    o[0] = std::atan2(r.s_c, r.c_c);
     o[1] = r.e_c;
-    o[2] = r.th_o;
+    o[2] = std::atan2(r.s_o, r.c_o);
     o[3] = r.e_o;
     o[4] = r.e3;
     o[5] = r.two ? 1.0 : 0.0;

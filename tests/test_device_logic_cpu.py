@@ -74,7 +74,10 @@ def test_sw_fall_matches_oracle(dl):
     assert np.array_equal(out[:, 5] == 1.0, two)
     dc = np.abs(np.angle(np.exp(1j * (out[:, 0] - tc))))
     assert dc.max() < 1e-9, dc.max()
+    do = np.abs(np.angle(np.exp(1j * (out[:, 2] - to))))
+    assert do[two].max() < 1e-9, do[two].max()
     assert np.abs(out[:, 1] - ec).max() < 1e-12
+    assert np.abs(out[two, 3] - eo[two]).max() < 1e-12
     assert np.abs(out[two, 4] - e3[two]).max() < 1e-12
 
 
