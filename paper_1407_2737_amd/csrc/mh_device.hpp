@@ -122,14 +122,15 @@ __device__ __forceinline__ double rcp64(double x) {
 }
 
 // FP32 seed of a zero of g / g' on the angle bracket (a, b), where the function is
-// negative at a iff a_neg: Newton kept inside the bracket, bisection when a step leaves
-// it, stopped once a step is below 1e-4 rad. Returns the angle and, in (so, co), its
-// sine and cosine with the last step applied to first order (about 1e-7 from the root),
-// which is where the double-precision polish starts.
+// negative at a iff a_neg: Newton from x0 (the middle of the bracket when x0 is not
+// inside it) kept inside the bracket, bisection when a step leaves it, stopped once a
+// step is below 1e-4 rad. Returns the angle and, in (so, co), its sine and cosine with
+// the last step applied to first order (about 1e-7 from the root), which is where the
+// double-precision polish starts.
 template <bool kDeriv>
-__device__ float seed_root(float a, float b, bool a_neg, float hx, float hy, float& so,
-                           float& co) {
-  float x = 0.5f * (a + b);
+__device__ float seed_root(float a, float b, bool a_neg, float hx, float hy, float x0,
+                           float& so, float& co) {
+  float x = (x0 > a && x0 < b) ? x0 : 0.5f * (a + b);
   for (int it = 0;; ++it) {
     float s, c, d;
     __sincosf(x, &s, &c);
@@ -158,10 +159,12 @@ __device__ float seed_root(float a, float b, bool a_neg, float hx, float hy, flo
 // FP64 zero of g / g' on the arc (a, b) (counter-clockwise, narrower than pi), where the
 // function is negative at a iff a_neg, started from direction x. Newton steps below
 // 1e-3 rad rotate the direction by a short Taylor series of the step's sine and cosine;
-// a step that is larger or leaves the arc is replaced by bisection. Stops when the step
-// is below 2e-16 rad, when a step below 1e-12 no longer halves the previous one (the
-// iterate is inside the rounding band of the root, which is wide where g' is small),
-// or when the arc is below 4e-16.
+// a step that is larger or leaves the arc is replaced by bisection. A step below 1e-12
+// rad is taken and ends the polish: Newton's quadratic convergence leaves the result
+// within (g''/2g') dx^2 of the root, far below the rounding of its sine and cosine
+// except right at a fold. It also stops when a step below 1e-12 no longer halves
+// the previous one (the iterate is inside the rounding band of the root, wide where g'
+// is small) or when the arc is below 4e-16.
 template <bool kDeriv>
 __device__ Dir polish_root(Dir a, Dir b, bool a_neg, double hx, double hy, Dir x) {
   if (!(cross(a, x) > 0.0 && cross(x, b) > 0.0)) x = unit(a.s + b.s, a.c + b.c);
@@ -185,6 +188,7 @@ __device__ Dir polish_root(Dir a, Dir b, bool a_neg, double hx, double hy, Dir x
       const Dir xn{x.s * cd + x.c * sd, x.c * cd - x.s * sd};
       if (cross(a, xn) > 0.0 && cross(xn, b) > 0.0) {
         x = xn;
+        if (adx < 1e-12) break;
         continue;
       }
     }
@@ -272,8 +276,10 @@ __device__ SWState sw_fall(double hx, double hy, Dir d0) {
   const float axf = (float)ax, hyf = (float)hy;
   const float kPiF = (float)kPi, kHalfPiF = (float)kHalfPi;
   const Dir east{0.0, 1.0}, north{1.0, 0.0}, west{0.0, -1.0};  // angles 0, pi/2, pi
+  // FP32 starts from the small-field linearisations of g about 0 (r1 = hy / (1 + hx)) and
+  // of g' about 3 pi / 4 (t* = 3 pi / 4 + (hx - hy) / (2 sqrt 2))
   float fs, fc;
-  seed_root<false>(0.f, kHalfPiF, true, axf, hyf, fs, fc);
+  seed_root<false>(0.f, kHalfPiF, true, axf, hyf, hyf * __builtin_amdgcn_rcpf(1.f + axf), fs, fc);
   const Dir d1 = polish_root<false>(east, north, true, ax, hy, unit(fs, fc));  // global min
   const double e1 = sw_energy(d1.s, d1.c, ax, hy);
   bool two = false;
@@ -282,7 +288,8 @@ __device__ SWState sw_fall(double hx, double hy, Dir d0) {
   if (astroid_bistable(ax, hy)) {
     // a direction between the saddle maximum and the metastable minimum in (pi/2, pi):
     // the FP32 zero t* of g', kept when g < 0 there in double precision, else polished
-    float ts = seed_root<true>(kHalfPiF, kPiF, true, axf, hyf, fs, fc);
+    float ts = seed_root<true>(kHalfPiF, kPiF, true, axf, hyf,
+                               0.75f * kPiF + 0.35355339f * (axf - hyf), fs, fc);
     Dir dt = unit(fs, fc);
     if (!(dt.s > 0.0 && dt.c < 0.0 && ts > kHalfPiF && ts < kPiF)) {
       ts = 0.75f * kPiF;
@@ -296,9 +303,16 @@ __device__ SWState sw_fall(double hx, double hy, Dir d0) {
     }
     if (gt < 0.0) {
       two = true;
-      seed_root<false>(kHalfPiF, ts, false, axf, hyf, fs, fc);
+      // starts at t* -+ sqrt(-2 g / g''), the zeros of g's quadratic expansion about its
+      // minimum t* (exact as the pair merges at the astroid)
+      float g2;
+      const float st = (float)dt.s, ct = (float)dt.c;
+      const float g0 = sw_fn<false>(st, ct, axf, hyf, g2);
+      sw_fn<true>(st, ct, axf, hyf, g2);
+      const float q = sqrtf(-2.f * g0 * __builtin_amdgcn_rcpf(g2));
+      seed_root<false>(kHalfPiF, ts, false, axf, hyf, ts - q, fs, fc);
       d2a = polish_root<false>(north, dt, false, ax, hy, unit(fs, fc));  // saddle maximum
-      seed_root<false>(ts, kPiF, true, axf, hyf, fs, fc);
+      seed_root<false>(ts, kPiF, true, axf, hyf, ts + q, fs, fc);
       d2b = polish_root<false>(dt, west, true, ax, hy, unit(fs, fc));  // metastable minimum
       e2a = sw_energy(d2a.s, d2a.c, ax, hy);
       e2b = sw_energy(d2b.s, d2b.c, ax, hy);
@@ -447,8 +461,10 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
     if (p.prob_form == 1) {
       P = -expm1(-p.nu0dt * exp(-a_c));
     } else {
-      const double sig = 1.0 / (1.0 + exp(a_c - a_o));
-      P = sig * (-expm1(-p.nu0dt * (exp(-a_c) + exp(-a_o))));
+      // sigma = 1 / (1 + e^(a_c - a_o)) = e^-a_c / (e^-a_c + e^-a_o); with both terms
+      // underflowed the bracket -expm1(-nu0 dt * 0) is 0 and so is P
+      const double xc = exp(-a_c), xo = exp(-a_o), sum = xc + xo;
+      P = sum > 0.0 ? (xc * rcp64(sum)) * (-expm1(-p.nu0dt * sum)) : 0.0;
     }
     const double u = philox_uniform(seed, stream, i, k);
     out.P = P;
