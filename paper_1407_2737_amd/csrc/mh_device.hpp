@@ -161,9 +161,9 @@ __device__ float seed_root(float a, float b, bool a_neg, float hx, float hy, flo
 // 1e-3 rad rotate the direction by a short Taylor series of the step's sine and cosine;
 // a step that is larger or leaves the arc is replaced by bisection. A step below 1e-12
 // rad is taken and ends the polish: Newton's quadratic convergence leaves the result
-// within (g''/2g') dx^2 of the root, far below the rounding of its sine and cosine
+// within (f''/2f') dx^2 of the root, far below the rounding of its sine and cosine
 // except right at a fold. It also stops when a step below 1e-12 no longer halves
-// the previous one (the iterate is inside the rounding band of the root, wide where g'
+// the previous one (the iterate is inside the rounding band of the root, wide where f'
 // is small) or when the arc is below 4e-16.
 template <bool kDeriv>
 __device__ Dir polish_root(Dir a, Dir b, bool a_neg, double hx, double hy, Dir x) {

@@ -393,12 +393,14 @@ __global__ void k_init(const SysDesc* __restrict__ systems) {
     m.z = sg * a.z;
     m.w = 0.0;
     s.m64[i] = m;
-    F4 f;
-    f.x = (float)m.x;
-    f.y = (float)m.y;
-    f.z = (float)m.z;
-    f.w = 0.f;
-    s.m32[i] = f;
+    if (s.m32) {
+      F4 f;
+      f.x = (float)m.x;
+      f.y = (float)m.y;
+      f.z = (float)m.z;
+      f.w = 0.f;
+      s.m32[i] = f;
+    }
     s.area[i] = 0.0;
     s.area[s.n + i] = 0.0;
   }
@@ -410,7 +412,7 @@ __global__ void k_init(const SysDesc* __restrict__ systems) {
 __global__ void k_sync32(const SysDesc* __restrict__ systems, int b) {
   const SysDesc s = systems[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= s.n) return;
+  if (i >= s.n || !s.m32) return;
   const D4 m = s.m64[(int64_t)b * s.stride + i];
   F4 f;
   f.x = (float)m.x;

@@ -83,12 +83,14 @@ __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur
   mn.z = r.mz;
   mn.w = 0.0;
   s.m64[(int64_t)nxt * s.stride + i] = mn;
-  F4 mf;
-  mf.x = (float)r.mx;
-  mf.y = (float)r.my;
-  mf.z = (float)r.mz;
-  mf.w = 0.f;
-  s.m32[(int64_t)nxt * s.stride + i] = mf;
+  if (s.m32) {
+    F4 mf;
+    mf.x = (float)r.mx;
+    mf.y = (float)r.my;
+    mf.z = (float)r.mz;
+    mf.w = 0.f;
+    s.m32[(int64_t)nxt * s.stride + i] = mf;
+  }
   if (k >= s.kept0) {
     double sum = s.area[i], comp = s.area[s.n + i];
     neumaier_add(sum, comp, s.Ms * Bext * (r.mx - mo.x));

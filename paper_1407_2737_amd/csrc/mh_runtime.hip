@@ -253,7 +253,7 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   const int64_t rows = (int64_t)n_kept(a->p) * a->p.steps_per_period;
   int e;
   if ((e = a->m64.ensure(sizeof(D4) * 2 * R * n))) return e;
-  if ((e = a->m32.ensure(sizeof(F4) * 2 * R * n))) return e;
+  if (a->p.precision == MH_FP32_FIELD && (e = a->m32.ensure(sizeof(F4) * 2 * R * n))) return e;
   if ((e = a->area.ensure(sizeof(double) * 2 * R * n))) return e;
   if ((e = a->recpart.ensure(sizeof(double) * R * rows * a->ntiles + 8))) return e;
   if ((e = a->rec.ensure(sizeof(double) * R * rows + 8))) return e;
@@ -301,7 +301,8 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.pos32 = a->pos32.as<F4>();
   s.axes = a->axes.as<D4>() + (r % a->n_axes_sets) * n;
   s.m64 = a->m64.as<D4>() + r * n;
-  s.m32 = a->m32.as<F4>() + r * n;
+  // FP32 moment copies exist only for the FP32 field form, which is their one reader
+  s.m32 = a->p.precision == MH_FP32_FIELD ? a->m32.as<F4>() + r * n : nullptr;
   s.area = a->area.as<double>() + r * 2 * n;
   const int64_t rows = (int64_t)n_kept(p) * p.steps_per_period;
   s.recpart = a->recpart.as<double>() + r * rows * a->ntiles;
