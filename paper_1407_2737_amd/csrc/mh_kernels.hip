@@ -54,6 +54,13 @@ __device__ __forceinline__ F4* mom_of<float>(const SysDesc& s) {
   return s.m32;
 }
 
+// 1/r for a squared distance in units of d. Distinct particles are at least one
+// diameter apart and padding sits at 1e15, so r2 is 0 (the pair j == i, masked by the
+// caller) or a normal number: the hardware reciprocal square root needs none of the
+// subnormal scaling that rsqrtf wraps around it.
+__device__ __forceinline__ float rsqrt_dist(float r2) { return __builtin_amdgcn_rsqf(r2); }
+__device__ __forceinline__ double rsqrt_dist(double r2) { return 1.0 / sqrt(r2); }
+
 // Eq. 1 term of source j on target i in reduced units (positions / d): accumulates
 // (3 (m.r) r / r^2 - m) / r^3 with r = p_j - p_i; a coincident pair (j == i)
 // contributes nothing.
@@ -62,11 +69,7 @@ __device__ __forceinline__ void dip_pair(T xi, T yi, T zi, const P4& pj, const M
                                          T& by, T& bz) {
   const T dx = (T)pj.x - xi, dy = (T)pj.y - yi, dz = (T)pj.z - zi;
   const T r2 = dx * dx + dy * dy + dz * dz;
-  T inv;
-  if constexpr (sizeof(T) == 4)
-    inv = rsqrtf(r2);
-  else
-    inv = (T)1 / sqrt(r2);
+  T inv = rsqrt_dist(r2);
   if constexpr (kGuard) inv = r2 > (T)0 ? inv : (T)0;
   const T inv2 = inv * inv;
   const T inv3 = inv2 * inv;
@@ -161,25 +164,61 @@ __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ sy
 // ---------------------------------------------------------------------------
 // Tiled form: two launches per step k.
 //
+// Pairs (target, e) for e = q, q + Q, ... < ce of one staged chunk, geometry shared by
+// the G replicas' moments; kGuard masks the pair j == i.
+template <typename T, int G, bool kGuard, int Q, int CH, typename P4>
+__device__ __forceinline__ void group_pairs_q(int q, int ce, T xi, T yi, T zi, const P4* spos,
+                                              const P4 (*smom)[CH], T* bx, T* by, T* bz) {
+#pragma unroll 2
+  for (int e = q; e < ce; e += Q) {
+    const P4 pj = spos[e];
+    const T dx = (T)pj.x - xi, dy = (T)pj.y - yi, dz = (T)pj.z - zi;
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    T inv = rsqrt_dist(r2);
+    if constexpr (kGuard) inv = r2 > (T)0 ? inv : (T)0;
+    const T inv2 = inv * inv;
+    const T inv3 = inv2 * inv;
+    const T s3 = (T)3 * inv2;
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const P4 mj = smom[r][e];
+      const T md = ((T)mj.x * dx + (T)mj.y * dy + (T)mj.z * dz) * s3;
+      bx[r] += inv3 * (md * dx - (T)mj.x);
+      by[r] += inv3 * (md * dy - (T)mj.y);
+      bz[r] += inv3 * (md * dz - (T)mj.z);
+    }
+  }
+}
+
 // k_field over (system, i-tile) blocks of 1024 threads. A block owns TI targets; its
 // 16 waves split the sources into Q = 16 * 64 / TI interleaved streams (lane l of wave
 // w: target l % TI, stream w * (64/TI) + l / TI). Sources are staged through LDS in
-// chunks of CH; partial fields are reduced across streams in LDS in a fixed order in
-// FP64 and written per particle. No block depends on another.
+// chunks of CH; partial fields are then reduced across streams in LDS, which reuses the
+// staging space, in a fixed two-level order in FP64 (sums of 16 streams, then of those
+// sums) and written per particle. No block depends on another.
 //
 // k_update, one thread per particle: steps iii-vii and the accumulations.
 // ---------------------------------------------------------------------------
 template <typename T, int TI, int G>
-__global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ systems,
+// At most 64 VGPRs where the unrolled loop allows it, so that two blocks share a CU.
+__global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ systems,
                                                 const int4* __restrict__ tiles,
                                                 const int64_t* __restrict__ kbase, int64_t koff) {
   using P4 = typename V4<T>::type;
   constexpr int L = 64 / TI;                       // streams per wave
   constexpr int Q = 16 * L;                        // streams per block
-  constexpr int CH = G == 1 ? 1024 : 512;          // sources per staged chunk
-  __shared__ P4 spos[CH];
-  __shared__ P4 smom[G][CH];
-  __shared__ T red[3][G][Q][TI];
+  constexpr int CH = G <= 3 ? 1024 : 512;          // sources per staged chunk
+  constexpr int NPART = Q / 16;                    // first-level sums of 16 streams
+  constexpr size_t kStage = sizeof(P4) * CH * (1 + G);
+  constexpr size_t kRed = sizeof(T) * 3 * G * Q * TI;
+  constexpr size_t kPart = sizeof(double) * 3 * G * NPART * TI;
+  constexpr size_t kLds = kStage > kRed + kPart ? kStage : kRed + kPart;
+  static_assert(Q % 16 == 0 && kRed % sizeof(double) == 0, "stream layout");
+  __shared__ __align__(16) unsigned char lds[kLds];
+  P4* spos = reinterpret_cast<P4*>(lds);                           // staged chunk
+  P4 (*smom)[CH] = reinterpret_cast<P4 (*)[CH]>(lds + sizeof(P4) * CH);
+  T (*red)[G][Q][TI] = reinterpret_cast<T (*)[G][Q][TI]>(lds);     // after the last chunk
+  double (*part)[G][NPART][TI] = reinterpret_cast<double (*)[G][NPART][TI]>(lds + kRed);
   const int4 tl = tiles[blockIdx.x];               // (first system, i-tile, replicas, part)
   const SysDesc& s = systems[tl.x];
   const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
@@ -245,32 +284,14 @@ __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ syst
         }
       } else {
         // geometry once per pair, applied to the G replicas' moments
-#pragma unroll 2
-        for (int e = q; e < ce; e += Q) {
-          const P4 pj = spos[e];
-          const T dx = (T)pj.x - xi, dy = (T)pj.y - yi, dz = (T)pj.z - zi;
-          const T r2 = dx * dx + dy * dy + dz * dz;
-          T inv;
-          if constexpr (sizeof(T) == 4)
-            inv = rsqrtf(r2);
-          else
-            inv = (T)1 / sqrt(r2);
-          if (self) inv = r2 > (T)0 ? inv : (T)0;
-          const T inv2 = inv * inv;
-          const T inv3 = inv2 * inv;
-          const T s3 = (T)3 * inv2;
-#pragma unroll
-          for (int r = 0; r < G; ++r) {
-            const P4 mj = smom[r][e];
-            const T md = ((T)mj.x * dx + (T)mj.y * dy + (T)mj.z * dz) * s3;
-            bx[r] += inv3 * (md * dx - (T)mj.x);
-            by[r] += inv3 * (md * dy - (T)mj.y);
-            bz[r] += inv3 * (md * dz - (T)mj.z);
-          }
-        }
+        if (self)
+          group_pairs_q<T, G, true, Q, CH>(q, ce, xi, yi, zi, spos, smom, bx, by, bz);
+        else
+          group_pairs_q<T, G, false, Q, CH>(q, ce, xi, yi, zi, spos, smom, bx, by, bz);
       }
     }
   }
+  __syncthreads();  // every read of the staged chunk is done before red overwrites it
 #pragma unroll
   for (int r = 0; r < G; ++r) {
     red[0][r][q][il] = bx[r];
@@ -278,16 +299,27 @@ __global__ __launch_bounds__(1024) void k_field(const SysDesc* __restrict__ syst
     red[2][r][q][il] = bz[r];
   }
   __syncthreads();
-  // fixed-order FP64 reduction over the streams: thread (r, target) for r < gn
+  // fixed-order FP64 reduction over the streams: thread (c, r, p, t) adds streams
+  // 16 p .. 16 p + 15, then thread (r, t) adds the NPART sums
+  if (tid < 3 * G * NPART * TI) {
+    const int t = tid % TI, pp = (tid / TI) % NPART, r = (tid / (TI * NPART)) % G;
+    const int c = tid / (TI * NPART * G);
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc += (double)red[c][r][pp * 16 + u][t];
+    part[c][r][pp][t] = acc;
+  }
+  __syncthreads();
   if (tid < G * TI) {
     const int r = tid / TI, t = tid % TI;
     const int ii = tl.y * TI + t;
     if (r < gn && ii < n) {
       double ax = 0, ay = 0, az = 0;
-      for (int qq = 0; qq < Q; ++qq) {
-        ax += (double)red[0][r][qq][t];
-        ay += (double)red[1][r][qq][t];
-        az += (double)red[2][r][qq][t];
+#pragma unroll
+      for (int pp = 0; pp < NPART; ++pp) {
+        ax += part[0][r][pp][t];
+        ay += part[1][r][pp][t];
+        az += part[2][r][pp][t];
       }
       D4 f;
       f.x = ax;
