@@ -54,6 +54,19 @@ __device__ __forceinline__ F4* mom_of<float>(const SysDesc& s) {
   return s.m32;
 }
 
+// Load through the global address space as one vector (the pointers come from
+// descriptors in memory, where the compiler cannot infer it and would emit flat loads).
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ F4 ldg(const F4* p) {
+  const f4v v = *(const __attribute__((address_space(1))) f4v*)p;
+  return F4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ D4 ldg(const D4* p) {
+  const d4v v = *(const __attribute__((address_space(1))) d4v*)p;
+  return D4{v.x, v.y, v.z, v.w};
+}
+
 // 1/r for a squared distance in units of d. Distinct particles are at least one
 // diameter apart and padding sits at 1e15, so r2 is 0 (the pair j == i, masked by the
 // caller) or a normal number: the hardware reciprocal square root needs none of the
@@ -249,23 +262,30 @@ __global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ s
       const int cn = min(CH, je - c0);
       __syncthreads();
       for (int j = tid; j < CH; j += 1024) {
-        P4 p;
-        if (j < cn) {
-          p = gpos[c0 + j];
-        } else {  // padding: far away and without moment, contributes exactly zero
-          p.x = p.y = p.z = (T)1e15;
-          p.w = (T)0;
-        }
+        // all loads first (padding entries read the chunk's last source), then the masks,
+        // so that the global loads are in flight together
+        const bool in = j < cn;
+        const int src = c0 + (in ? j : cn - 1);
+        P4 p = ldg(gpos + src);
+        P4 m[G];
+#pragma unroll
+        for (int r = 0; r < G; ++r) m[r] = ldg(gmom[r] + src);
+        // padding: far away and without moment, contributes exactly zero. The masks are
+        // arithmetic (finite data times 0 or 1) so that the loads stay unconditional.
+        const T keep = in ? (T)1 : (T)0, far = in ? (T)0 : (T)1e15;
+        p.x = p.x * keep + far;
+        p.y = p.y * keep + far;
+        p.z = p.z * keep + far;
+        p.w = p.w * keep;
         spos[j] = p;
 #pragma unroll
         for (int r = 0; r < G; ++r) {
-          P4 m;
-          if (j < cn && r < gn) {
-            m = gmom[r][c0 + j];
-          } else {
-            m.x = m.y = m.z = m.w = (T)0;
-          }
-          smom[r][j] = m;
+          const T mk = r < gn ? keep : (T)0;
+          m[r].x *= mk;
+          m[r].y *= mk;
+          m[r].z *= mk;
+          m[r].w *= mk;
+          smom[r][j] = m[r];
         }
       }
       __syncthreads();
