@@ -26,9 +26,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak, FLOP/s
-FLOPS_PER_PAIR = 30             # Eq. 1 pair term as evaluated, one replica
+FLOPS_PER_PAIR = 30             # Eq. 1 pair term, one replica: GEOM_FLOPS + MOMENT_FLOPS
 GEOM_FLOPS = 12                 # shared pair geometry: 3 differences, 5 for r^2, rsqrt, r^-2, r^-3, 3 r^-2
 MOMENT_FLOPS = 18               # per replica: 5 for m.r, 1 scale, 4 per component x 3
+
+# HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE over the default workload (one period), each scaled by what the counter
+# reads for a 256 MiB elementwise copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).
+# Tied to the kernel as measured: k_field<float,16,3> with three source parts per tile
+# (profiles/k_field_config2_fp32.md); None for kernels without such a measurement.
+TRAFFIC_BYTES = {"k_field<float,16,3>": (1351.94 * 2.000 + 1406.25 * 1.000) * 1024}
 
 
 def cpu_baseline(assemblies, budget_s=15.0):
@@ -120,7 +127,8 @@ def main():
                         + MOMENT_FLOPS * pairs_per_launch)
     achieved = flops_per_launch / avg_launch_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+                "traffic": TRAFFIC_BYTES.get("k_field<float,16,3>"),
                 "kernel": "k_field<float,16,3>", "avg_launch_us": avg_launch_s * 1e6,
                 "launches": launches, "flops_per_launch": flops_per_launch,
                 "update_kernel_avg_us": ms_update * 1e3 / max(launches_u, 1)}
