@@ -132,6 +132,15 @@ def main():
                 "kernel": "k_field<float,16,3>", "avg_launch_us": avg_launch_s * 1e6,
                 "launches": launches, "flops_per_launch": flops_per_launch,
                 "update_kernel_avg_us": ms_update * 1e3 / max(launches_u, 1)}
+    # per-particle area against depth below the membrane, 1 - |r|/R (the output of this
+    # workload): mean per-particle area of each amplitude in depth bins of the last run
+    depth = 1.0 - np.linalg.norm(w2.pos, axis=1) / w2.radius
+    edges = [0.0, 0.05, 0.1, 0.2, 0.3, 0.5, 1.0]
+    which = np.digitize(depth, edges[1:-1])
+    profile = {}
+    for r, h in enumerate(amps):
+        a_np = asm.area_per_np(r)
+        profile[f"{h * 1e3:g} mT"] = [float(a_np[which == b].mean()) for b in range(len(edges) - 1)]
     line = {
         "metric": "NP·steps/s (dipolar+kMC)",
         "value": value,
@@ -149,7 +158,11 @@ def main():
                                "random 3-D axes, 10/20/40 mT batched, 100 kHz, "
                                f"{args.periods} periods x 2000 steps",
                    "n_particles_total": n_total, "steps_per_run": steps_per_run,
-                   "sar_W_per_g": [r["sar"] / 1e3 for r in res]},
+                   "sar_W_per_g": [r["sar"] / 1e3 for r in res],
+                   "area_Jm3_vs_depth": {"depth_edges": edges,
+                                         "count": [int((which == b).sum())
+                                                   for b in range(len(edges) - 1)],
+                                         **profile}},
         "roofline": roofline,
     }
     if not args.no_cpu:
@@ -269,6 +282,18 @@ def bench_c3(args, mh, W):
             "frac": FLOPS_PER_PAIR * pairs / avg / PEAK_FP32_VECTOR, "traffic": None,
             "kernel": "k_field<float>", "avg_launch_us": avg * 1e6, "launches": launches,
             "update_kernel_avg_us": ms_u * 1e3 / max(lu, 1), "resident_ms": ms_r}
+    # field error of this form on replica 0's final moments, against the FP64 field
+    # kernel (which the parity tests hold within 1e-13 of the FP64 oracle): relative
+    # Frobenius norm and the largest per-particle error over the rms field
+    m0 = asm.moments(0)
+    b_form = asm.debug_field(m0)
+    a64 = mh.Assembly(ctx, a4.pos, a4.axes[:n], mh.params_from_material(a4.mat, mh.FP64))
+    b_64 = a64.debug_field(m0)
+    a64.close()
+    db = b_form - b_64
+    field_err = {"rel_frobenius": float(np.linalg.norm(db) / np.linalg.norm(b_64)),
+                 "max_over_rms": float(np.linalg.norm(db, axis=1).max()
+                                       / np.sqrt((b_64 ** 2).sum(axis=1).mean()))}
     line = {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -285,6 +310,7 @@ def bench_c4(args, mh, W):
     """Replica-batched form: N=4096 in a 200 nm lysosome at phi=10 %, one axis set per
     replica, R replicas on independent Philox streams; W.M on MFMA (c4) or the plain
     FP32 N-body kernels on the same replicas (c4plain)."""
+    import numpy as np
     R = args.replicas
     a4 = W.config4(n_axes_sets=R)
     a4.mat.n_periods = args.periods
@@ -329,6 +355,18 @@ def bench_c4(args, mh, W):
                 "unit": "TFLOP/s", "frac": alg / avg / PEAK_FP32_VECTOR, "traffic": None,
                 "kernel": "k_field<float>", "avg_launch_us": avg * 1e6, "launches": launches,
                 "update_kernel_avg_us": ms_u * 1e3 / max(lu, 1)}
+    # field error of this form on replica 0's final moments, against the FP64 field
+    # kernel (which the parity tests hold within 1e-13 of the FP64 oracle): relative
+    # Frobenius norm and the largest per-particle error over the rms field
+    m0 = asm.moments(0)
+    b_form = asm.debug_field(m0)
+    a64 = mh.Assembly(ctx, a4.pos, a4.axes[:n], mh.params_from_material(a4.mat, mh.FP64))
+    b_64 = a64.debug_field(m0)
+    a64.close()
+    db = b_form - b_64
+    field_err = {"rel_frobenius": float(np.linalg.norm(db) / np.linalg.norm(b_64)),
+                 "max_over_rms": float(np.linalg.norm(db, axis=1).max()
+                                       / np.sqrt((b_64 ** 2).sum(axis=1).mean()))}
     line = {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -337,7 +375,8 @@ def bench_c4(args, mh, W):
             "data": "synthetic",
             "config": {"workload": f"config4 ({args.workload}): N={n}, R={R} replicas, 200 nm, "
                                    f"phi=10%, d={a4.mat.d * 1e9:.2f} nm, 20 mT, {args.periods} periods",
-                       "sar_W_per_g": res["sar"] / 1e3, "sar_se_W_per_g": res["sar_se"] / 1e3},
+                       "sar_W_per_g": res["sar"] / 1e3, "sar_se_W_per_g": res["sar_se"] / 1e3,
+                       "field_error_vs_fp64": field_err},
             "roofline": roof}
     print(json.dumps(line), flush=True)
 

@@ -110,6 +110,20 @@ int mh_set_replica_fields(mh_asm* a, int64_t count, const double* mu0Hmax);
 int mh_run_batch(mh_asm* const* asms, int32_t count, const int64_t* n_replicas,
                  const uint64_t* seeds, void* hip_stream);
 
+/* Deterministic mean-magnetisation loops of non-interacting particles: the paper's
+ * validation method (Sec. II.3, Fig. 1(c)-(d)), the loop of an infinite number of
+ * particles. Instead of drawing one well per particle, each particle carries the
+ * probability of each well; every step both weighted moments fall in the applied field
+ * (steps iii-v), weights reaching the same minimum are pooled, and Eq. 5 moves weight
+ * across the barrier in both directions (steps vi-vii). Replica r uses axis set
+ * r mod n_axes_sets and, after mh_set_replica_fields, its own amplitude; no random
+ * numbers are drawn. Results are read with mh_get_loop, mh_get_sar,
+ * mh_get_replica_areas and mh_get_area_per_np as after mh_run_loops; mh_get_moments
+ * gives the expected moments. Asynchronous like mh_run_loops (hip_stream NULL = the
+ * library's stream). MH_EINVAL unless params.interactions == 0 and Keff > 0, or for
+ * n_replicas outside [1, 65535]. */
+int mh_run_mean_loop(mh_asm* a, int64_t n_replicas, void* hip_stream);
+
 /* Waits for the assembly's last run. */
 int mh_sync(mh_asm* a);
 
@@ -126,6 +140,13 @@ int mh_get_sar(mh_asm* a, double* sar_Wkg, double* sar_se, double* area_Jm3, dou
 
 /* Per-replica loop areas (n_replicas values, J/m^3). */
 int mh_get_replica_areas(mh_asm* a, double* area);
+
+/* Per-particle loop areas of one replica (n values, J/m^3, mean over its kept periods):
+ * the energy each particle absorbs, Sec. II.2 area rule applied to one moment, which
+ * the per-particle analyses of Sec. III (area against depth below the lysosome
+ * membrane) average. MH_EINVAL for a replica outside the last run, MH_ENOTREADY before
+ * any run. */
+int mh_get_area_per_np(mh_asm* a, int64_t replica, double* area_per_np);
 
 /* Current moments of one replica (n x 3). */
 int mh_get_moments(mh_asm* a, int64_t replica, double* m);
@@ -198,8 +219,9 @@ int mh_server_destroy(mh_server* s);
 /* Launch timing (diagnostics for roofline reports). When on, every step-kernel launch
  * is bracketed by a pair of HIP events on the stream it runs on. mh_ctx_get_timing
  * waits for the recorded launches of one kind (0: tiled dipolar-field kernel, 1: resident
- * whole-run launch, 2: interaction-matrix step, 3: per-particle update kernel), returns
- * their summed duration (ms) and count. mh_ctx_set_timing clears the record. */
+ * whole-run launch, 2: interaction-matrix product, 3: per-particle update kernel,
+ * 4: update kernel of the interaction-matrix form, 5: mean-magnetisation loop launch),
+ * returns their summed duration (ms) and count. mh_ctx_set_timing clears the record. */
 int mh_ctx_set_timing(mh_ctx* ctx, int on);
 int mh_ctx_get_timing(mh_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
 

@@ -25,7 +25,7 @@ SYMBOLS = [
     "mh_get_replica_areas", "mh_get_moments", "mh_debug_steps", "mh_debug_philox",
     "mh_debug_sw", "mh_debug_field", "mh_strerror", "mh_ctx_set_timing", "mh_ctx_get_timing",
     "mh_server_create", "mh_server_submit", "mh_server_poll", "mh_server_destroy",
-    "mh_set_replica_fields",
+    "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
 ]
 
 
@@ -93,6 +93,8 @@ def _lib():
             "mh_get_sar": ([vp, dp, dp, dp, dp, dp], C.c_int),
             "mh_get_replica_areas": ([vp, dp], C.c_int),
             "mh_get_moments": ([vp, i64, dp], C.c_int),
+            "mh_get_area_per_np": ([vp, i64, dp], C.c_int),
+            "mh_run_mean_loop": ([vp, i64, vp], C.c_int),
             "mh_debug_steps": ([vp, i64, u64, i64, i64, dp, dp], C.c_int),
             "mh_debug_philox": ([vp, u64, u64, i64, u64p, u64p], C.c_int),
             "mh_debug_sw": ([vp, i64, dp, dp, dp, dp], C.c_int),
@@ -210,6 +212,11 @@ class Assembly:
         _check(_lib().mh_run_loops(self._h, n_replicas, seed, stream), "mh_run_loops")
         self.R = n_replicas
 
+    def run_mean_loop(self, n_replicas: int = 1, stream=None):
+        """Deterministic mean-magnetisation loops (non-interacting particles)."""
+        _check(_lib().mh_run_mean_loop(self._h, n_replicas, stream), "mh_run_mean_loop")
+        self.R = n_replicas
+
     def sync(self):
         _check(_lib().mh_sync(self._h), "mh_sync")
 
@@ -233,6 +240,12 @@ class Assembly:
     def replica_areas(self) -> np.ndarray:
         out = np.empty(self.R)
         _check(_lib().mh_get_replica_areas(self._h, _dp(out)), "mh_get_replica_areas")
+        return out
+
+    def area_per_np(self, replica: int = 0) -> np.ndarray:
+        """Per-particle loop areas of one replica, J/m^3 (mean over kept periods)."""
+        out = np.empty(self.n)
+        _check(_lib().mh_get_area_per_np(self._h, replica, _dp(out)), "mh_get_area_per_np")
         return out
 
     def moments(self, replica: int = 0) -> np.ndarray:

@@ -389,6 +389,83 @@ struct NPResult {
   int two;
 };
 
+// Step iii: the working plane (n, u) of a particle with axis n in the field B, the
+// reduced in-plane field (hx, hy) and the direction of the moment m in that plane.
+// When B has no component across the axis (|B_perp| <= 1e-12 max(|B|, mu0 H_K),
+// compared in squares) u is the unit part of m across the axis, else n x e with e the
+// coordinate axis least aligned with n (first on ties); deg marks that case.
+struct Plane {
+  double ux, uy, uz, hx, hy;
+  Dir d0;
+  bool deg;
+};
+
+__device__ __forceinline__ Plane working_plane(const NPParams& p, double Bx, double By, double Bz,
+                                               double nx, double ny, double nz, double mx,
+                                               double my, double mz) {
+  Plane w;
+  const double bpar = Bx * nx + By * ny + Bz * nz;
+  double px = Bx - bpar * nx, py = By - bpar * ny, pz = Bz - bpar * nz;
+  const double bp2 = px * px + py * py + pz * pz;
+  const double bn2 = Bx * Bx + By * By + Bz * Bz;
+  w.deg = !(bp2 > 1e-24 * fmax(bn2, p.BK * p.BK));
+  if (!w.deg) {
+    const double inv = rsqrt64(bp2);
+    w.ux = px * inv;
+    w.uy = py * inv;
+    w.uz = pz * inv;
+    w.hy = bp2 * inv * p.BK_inv;
+  } else {
+    w.hy = 0.0;
+    const double mn = mx * nx + my * ny + mz * nz;
+    double vx = mx - mn * nx, vy = my - mn * ny, vz = mz - mn * nz;
+    const double vn = sqrt(vx * vx + vy * vy + vz * vz);
+    if (vn > 1e-12) {
+      w.ux = vx / vn;
+      w.uy = vy / vn;
+      w.uz = vz / vn;
+    } else {
+      const double ax = fabs(nx), ay = fabs(ny), az = fabs(nz);
+      int c = 0;
+      if (ay < ax) c = 1;
+      if (az < (c == 0 ? ax : ay)) c = 2;
+      const double ex = c == 0, ey = c == 1, ez = c == 2;
+      vx = ny * ez - nz * ey;
+      vy = nz * ex - nx * ez;
+      vz = nx * ey - ny * ex;
+      const double wn = sqrt(vx * vx + vy * vy + vz * vz);
+      w.ux = vx / wn;
+      w.uy = vy / wn;
+      w.uz = vz / wn;
+    }
+  }
+  w.hx = bpar * p.BK_inv;
+  w.d0 = dir_of(mx * w.ux + my * w.uy + mz * w.uz, mx * nx + my * ny + mz * nz);
+  return w;
+}
+
+// Eq. 5 for both directions between the wells c and o (a = barrier / k_B T): P_co
+// to leave c for o and P_oc the reverse. sigma = 1 / (1 + e^(a_c - a_o)) is formed as
+// e^-a_c / (e^-a_c + e^-a_o); with both terms underflowed the bracket
+// -expm1(-nu0 dt * 0) is 0 and so are both. The single-rate form is -expm1(-nu0 dt e^-a).
+__device__ __forceinline__ void transition_pair(const NPParams& p, double a_c, double a_o,
+                                                double& P_co, double& P_oc) {
+  const double xc = exp(-a_c), xo = exp(-a_o);
+  if (p.prob_form == 1) {
+    P_co = -expm1(-p.nu0dt * xc);
+    P_oc = -expm1(-p.nu0dt * xo);
+    return;
+  }
+  const double sum = xc + xo;
+  if (!(sum > 0.0)) {
+    P_co = P_oc = 0.0;
+    return;
+  }
+  const double r = rcp64(sum), q = -expm1(-p.nu0dt * sum);
+  P_co = (xc * r) * q;
+  P_oc = (xo * r) * q;
+}
+
 __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz, double nx,
                               double ny, double nz, double mx, double my, double mz,
                               uint64_t seed, uint64_t stream, int64_t i, int64_t k) {
@@ -409,48 +486,10 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
     }
     return out;
   }
-  // step iii: working plane (n, u2)
-  const double bpar = Bx * nx + By * ny + Bz * nz;
-  double px = Bx - bpar * nx, py = By - bpar * ny, pz = Bz - bpar * nz;
-  // |B_perp| > 1e-12 max(|B|, mu0 H_K), compared in squares
-  const double bp2 = px * px + py * py + pz * pz;
-  const double bn2 = Bx * Bx + By * By + Bz * Bz;
-  double ux, uy, uz, hy;
-  if (bp2 > 1e-24 * fmax(bn2, p.BK * p.BK)) {
-    const double inv = rsqrt64(bp2);
-    ux = px * inv;
-    uy = py * inv;
-    uz = pz * inv;
-    hy = bp2 * inv * p.BK_inv;
-  } else {
-    hy = 0.0;
-    const double mn = mx * nx + my * ny + mz * nz;
-    double vx = mx - mn * nx, vy = my - mn * ny, vz = mz - mn * nz;
-    const double vn = sqrt(vx * vx + vy * vy + vz * vz);
-    if (vn > 1e-12) {
-      ux = vx / vn;
-      uy = vy / vn;
-      uz = vz / vn;
-    } else {
-      // n x e, e = coordinate axis least aligned with n (first on ties)
-      const double ax = fabs(nx), ay = fabs(ny), az = fabs(nz);
-      int c = 0;
-      if (ay < ax) c = 1;
-      if (az < (c == 0 ? ax : ay)) c = 2;
-      const double ex = c == 0, ey = c == 1, ez = c == 2;
-      vx = ny * ez - nz * ey;
-      vy = nz * ex - nx * ez;
-      vz = nx * ey - ny * ex;
-      const double wn = sqrt(vx * vx + vy * vy + vz * vz);
-      ux = vx / wn;
-      uy = vy / wn;
-      uz = vz / wn;
-    }
-  }
-  const double hx = bpar * p.BK_inv;
-  const Dir d0 = dir_of(mx * ux + my * uy + mz * uz, mx * nx + my * ny + mz * nz);
+  // step iii
+  const Plane w = working_plane(p, Bx, By, Bz, nx, ny, nz, mx, my, mz);
   // steps iv-v
-  const SWState sw = sw_fall(hx, hy, d0);
+  const SWState sw = sw_fall(w.hx, w.hy, w.d0);
   double s = sw.s_c, c = sw.c_c;
   out.two = sw.two;
   // steps vi-vii
@@ -474,10 +513,65 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
       out.jump = 1;
     }
   }
-  out.mx = c * nx + s * ux;
-  out.my = c * ny + s * uy;
-  out.mz = c * nz + s * uz;
+  out.mx = c * nx + s * w.ux;
+  out.my = c * ny + s * w.uy;
+  out.mz = c * nz + s * w.uz;
   return out;
+}
+
+// Mean-magnetisation (master-equation) state of one non-interacting particle: two
+// weighted moments, wells A and B (Sec. II.3, the paper's validation method).
+struct MasterState {
+  double ax, ay, az, bx, by, bz, wa, wb;
+};
+
+__device__ __forceinline__ void master_init(MasterState& q, double nx, double ny, double nz) {
+  const double sg = nx >= 0.0 ? 1.0 : -1.0;
+  q.ax = q.bx = sg * nx;
+  q.ay = q.by = sg * ny;
+  q.az = q.bz = sg * nz;
+  q.wa = 1.0;
+  q.wb = 0.0;
+}
+
+// One step in the applied field Bext (along x): both weighted moments fall (steps
+// iii-v; B uses A's plane unless the field lies along the axis, where the plane follows
+// each moment and the minima are +-n), weights reaching the same minimum are pooled,
+// Eq. 5 moves w_c P(c->o) from each well to the other (steps vi-vii), and with one
+// minimum all weight goes to it. Requires K > 0. Returns the expected m_x.
+__device__ __forceinline__ double master_step(const NPParams& p, double Bext, double nx,
+                                              double ny, double nz, MasterState& q) {
+  const Plane pa = working_plane(p, Bext, 0.0, 0.0, nx, ny, nz, q.ax, q.ay, q.az);
+  const SWState fa = sw_fall(pa.hx, pa.hy, pa.d0);
+  Plane pb = pa;
+  if (pa.deg)
+    pb = working_plane(p, Bext, 0.0, 0.0, nx, ny, nz, q.bx, q.by, q.bz);
+  else
+    pb.d0 = dir_of(q.bx * pa.ux + q.by * pa.uy + q.bz * pa.uz, q.bx * nx + q.by * ny + q.bz * nz);
+  const SWState fb = sw_fall(pb.hx, pb.hy, pb.d0);
+  // the same (hx, hy) give bitwise the same minima, so the pooling test is exact
+  const bool same = fb.s_c == fa.s_c && fb.c_c == fa.c_c;
+  double w1 = q.wa + (same ? q.wb : 0.0), w2 = same ? 0.0 : q.wb;
+  if (!fa.two) {
+    w1 = 1.0;
+    w2 = 0.0;
+  } else if (p.thermal) {
+    double P12, P21;
+    transition_pair(p, p.beta * (fa.e3 - fa.e_c), p.beta * (fa.e3 - fa.e_o), P12, P21);
+    const double n1 = w1 * (1.0 - P12) + w2 * P21;
+    const double n2 = w2 * (1.0 - P21) + w1 * P12;
+    w1 = n1;
+    w2 = n2;
+  }
+  q.ax = fa.c_c * nx + fa.s_c * pa.ux;
+  q.ay = fa.c_c * ny + fa.s_c * pa.uy;
+  q.az = fa.c_c * nz + fa.s_c * pa.uz;
+  q.bx = fa.c_o * nx + fa.s_o * pa.ux;
+  q.by = fa.c_o * ny + fa.s_o * pa.uy;
+  q.bz = fa.c_o * nz + fa.s_o * pa.uz;
+  q.wa = w1;
+  q.wb = w2;
+  return w1 * q.ax + w2 * q.bx;
 }
 
 // Neumaier compensated accumulation: sum += x with running compensation.

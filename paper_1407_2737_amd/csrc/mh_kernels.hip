@@ -431,6 +431,48 @@ __global__ void k_area_per_np(const double* __restrict__ area, int n, int R, int
   out[i] = n_kept > 0 ? a / ((double)R * n_kept) : 0.0;
 }
 
+// Deterministic mean-magnetisation loop of non-interacting particles (the paper's
+// validation method, Sec. II.3 and Fig. 1(c)-(d)): one thread carries one particle of
+// one replica through every step of the run. Its state is two weighted moments (wells A
+// and B, all weight in A at the start); each step both fall in the applied field
+// (steps iii-v), the weights are pooled by the minimum they reach, and Eq. 5 moves
+// w_c P(c->o) from each well to the other (steps vi-vii); with one minimum all weight
+// goes to it. The expected m_x feeds the loop record (fixed-order block sums per kept
+// step) and the per-particle compensated area, as a kMC run does, so the same
+// finalisation gives the loop, the area and the SAR. Requires K > 0 and no
+// interactions (the launcher's caller checks both).
+__global__ __launch_bounds__(256) void k_master(const SysDesc* __restrict__ systems) {
+  __shared__ double red[4];
+  const SysDesc& s = systems[blockIdx.y];
+  if ((int)blockIdx.x * 256 >= s.n) return;  // whole block past this system's particles
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool act = i < s.n;
+  const D4 nn = s.axes[act ? i : s.n - 1];  // idle lanes shadow the last particle
+  MasterState q;
+  master_init(q, nn.x, nn.y, nn.z);
+  double mx_prev = q.ax, sum = 0.0, comp = 0.0;
+  for (int k = 0; k < s.total_steps; ++k) {
+    const double Bext = applied_field(s, k);
+    const double mx = master_step(s.np, Bext, nn.x, nn.y, nn.z, q);
+    if (k >= s.kept0) {
+      neumaier_add(sum, comp, s.Ms * Bext * (mx - mx_prev));
+      const double t = block_sum_256(act ? mx : 0.0, red);
+      if (threadIdx.x == 0) s.recpart[(int64_t)(k - s.kept0) * s.ntiles + blockIdx.x] = t;
+    }
+    mx_prev = mx;
+  }
+  if (act) {
+    s.area[i] = sum;
+    s.area[s.n + i] = comp;
+    D4 m;  // expected moment after the last step, in the buffer that step writes
+    m.x = q.wa * q.ax + q.wb * q.bx;
+    m.y = q.wa * q.ay + q.wb * q.by;
+    m.z = q.wa * q.az + q.wb * q.bz;
+    m.w = 0.0;
+    s.m64[(int64_t)(s.total_steps & 1) * s.stride + i] = m;
+  }
+}
+
 // Start of a run: m_i = sign(n_i . x) n_i in buffer 0 (both precisions), zero the
 // area accumulators and the loop-record partials.
 __global__ void k_init(const SysDesc* __restrict__ systems) {
@@ -593,6 +635,12 @@ hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st) 
 hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st) {
   if (nsys == 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize_sys, dim3(nsys), dim3(256), 0, st, d_sys);
+  return hipGetLastError();
+}
+
+hipError_t launch_master(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st) {
+  if (nsys == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_master, dim3((nmax + 255) / 256, nsys), dim3(256), 0, st, d_sys);
   return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ hipError_t launch_wm_pack(const SysDesc* d_sys, int R, int n, const WMArgs& g, i
                           hipStream_t st);
 hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st);
 hipError_t launch_init(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st);
+hipError_t launch_master(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st);
 hipError_t launch_sync32(const SysDesc* d_sys, int nsys, int nmax, int b, hipStream_t st);
 hipError_t launch_finalize_asm(const double* d_sys_area, int R, double* d_out, hipStream_t st);
 hipError_t launch_area_per_np(const double* d_area, int n, int R, int n_kept, double* d_out,
@@ -632,10 +633,64 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   return MH_OK;
 }
 
+// Deterministic mean-magnetisation loops (k_master): state, accumulators and record
+// only, no field buffers; replica r uses axis set r mod n_axes_sets and its amplitude.
+int run_mean_loop(mh_asm* a, int64_t R, hipStream_t st) {
+  mh_ctx* c = a->ctx;
+  if (set_dev(c)) return MH_EDEVICE;
+  if (!st) st = c->stream;
+  const int64_t n = a->n;
+  const int64_t rows = (int64_t)n_kept(a->p) * a->p.steps_per_period;
+  int e;
+  if ((e = a->m64.ensure(sizeof(D4) * 2 * R * n)) || (e = a->area.ensure(sizeof(double) * 2 * R * n)))
+    return e;
+  a->resident = 0;
+  a->nsplit = 1;
+  a->ntiles = (int)((n + 255) / 256);
+  if ((e = a->recpart.ensure(sizeof(double) * R * rows * a->ntiles + 8)) ||
+      (e = a->rec.ensure(sizeof(double) * R * rows + 8)) ||
+      (e = a->sys_area.ensure(sizeof(double) * R)) || (e = a->stats.ensure(sizeof(double) * 4)))
+    return e;
+  a->R = R;
+  a->seed = 0;
+  a->k_origin = 0;
+  std::vector<SysDesc> all;
+  for (int64_t r = 0; r < R; ++r) {
+    SysDesc d = make_desc(a, r);
+    d.field = nullptr;
+    d.m32 = nullptr;
+    all.push_back(d);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return MH_EDEVICE;  // stage reuse
+  if ((e = c->h_stage.ensure(sizeof(SysDesc) * R + 256)) || (e = c->d_sys.ensure(sizeof(SysDesc) * R + 256)))
+    return e;
+  size_t off = 0;
+  SysDesc* d_all = stage_upload(c, all, off, st);
+  if (launch_init(d_all, (int)R, (int)n, st) != hipSuccess) return MH_EDEVICE;
+  const int tq = timing_begin(c, st, 5);
+  if (launch_master(d_all, (int)R, (int)n, st) != hipSuccess) return MH_EDEVICE;
+  timing_end(c, st, tq);
+  if (launch_finalize(d_all, (int)R, st) != hipSuccess ||
+      launch_finalize_asm(a->sys_area.as<double>(), (int)R, a->stats.as<double>(), st) != hipSuccess)
+    return MH_EDEVICE;
+  if (!a->done && hipEventCreateWithFlags(&a->done, hipEventDisableTiming) != hipSuccess)
+    return MH_EDEVICE;
+  if (hipEventRecord(a->done, st) != hipSuccess) return MH_EDEVICE;
+  a->ran = true;
+  a->state_parity = (int)(total_steps(a->p) & 1);
+  return MH_OK;
+}
+
 }  // namespace
 
 
 extern "C" {
+
+int mh_run_mean_loop(mh_asm* a, int64_t n_replicas, void* hip_stream) {
+  if (!a || n_replicas < 1 || n_replicas > 65535) return MH_EINVAL;
+  if (a->p.interactions != 0 || !(a->p.Keff > 0)) return MH_EINVAL;
+  return run_mean_loop(a, n_replicas, (hipStream_t)hip_stream);
+}
 
 int mh_ctx_set_timing(mh_ctx* c, int on) {
   if (!c) return MH_EINVAL;
@@ -874,6 +929,23 @@ int mh_get_replica_areas(mh_asm* a, double* area) {
                  hipSuccess
              ? MH_OK
              : MH_EDEVICE;
+}
+
+int mh_get_area_per_np(mh_asm* a, int64_t replica, double* area_per_np) {
+  if (!a || !area_per_np) return MH_EINVAL;
+  int e = mh_sync(a);
+  if (e) return e;
+  if (replica < 0 || replica >= a->R) return MH_EINVAL;
+  if ((e = a->tmp.ensure(sizeof(double) * a->n))) return e;
+  // the replica's accumulators (sum, compensation) as a one-replica set
+  if (launch_area_per_np(a->area.as<double>() + replica * 2 * a->n, (int)a->n, 1, n_kept(a->p),
+                         a->tmp.as<double>(), a->ctx->stream) != hipSuccess)
+    return MH_EDEVICE;
+  if (hipMemcpyAsync(area_per_np, a->tmp.p, sizeof(double) * a->n, hipMemcpyDeviceToHost,
+                     a->ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(a->ctx->stream) != hipSuccess)
+    return MH_EDEVICE;
+  return MH_OK;
 }
 
 int mh_get_moments(mh_asm* a, int64_t replica, double* m) {

@@ -3,6 +3,7 @@
 // Test infrastructure only: the GPU library is built from the same header by hipcc.
 #include <cmath>
 #include <cstdint>
+#include <vector>
 #define __device__
 #define __host__
 #define __forceinline__ inline
@@ -74,5 +75,43 @@ void dl_update(int64_t n, const double* B, const double* ax, const double* m, do
     o[4] = r.jump;
     o[5] = r.two;
   }
+}
+
+// Mean-magnetisation loop of n non-interacting particles, as the GPU kernel runs it:
+// per step every particle's master_step, then the loop record (M_S <m_x> for each
+// kept step, n_kept x S) and the per-particle compensated area averaged over particles
+// and kept periods (area_out[0], J/m^3).
+void dl_master(int64_t n, const double* ax, double Ms, double BK, double beta, double nu0dt,
+               int prob_form, int thermal, double Bmax, int S, int n_periods, int n_discard,
+               int static_field, double* M_out, double* area_out) {
+  mh::NPParams p;
+  p.BK = BK;
+  p.BK_inv = 1.0 / BK;
+  p.beta = beta;
+  p.nu0dt = nu0dt;
+  p.prob_form = prob_form;
+  p.thermal = thermal;
+  p.aniso = 1;
+  std::vector<mh::MasterState> q((size_t)n);
+  std::vector<double> prev((size_t)n), sum((size_t)n, 0.0), comp((size_t)n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    mh::master_init(q[i], ax[3 * i], ax[3 * i + 1], ax[3 * i + 2]);
+    prev[i] = q[i].ax;
+  }
+  const int total = S * n_periods, kept0 = S * n_discard;
+  for (int k = 0; k < total; ++k) {
+    const double Bext = static_field ? Bmax : Bmax * std::cos(2.0 * mh::kPi * (double)k / (double)S);
+    double msum = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double mx = mh::master_step(p, Bext, ax[3 * i], ax[3 * i + 1], ax[3 * i + 2], q[i]);
+      if (k >= kept0) mh::neumaier_add(sum[i], comp[i], Ms * Bext * (mx - prev[i]));
+      prev[i] = mx;
+      msum += mx;
+    }
+    if (k >= kept0) M_out[k - kept0] = Ms * msum / (double)n;
+  }
+  double a = 0.0;
+  for (int64_t i = 0; i < n; ++i) a += sum[i] + comp[i];
+  area_out[0] = a / ((double)n * (n_periods - n_discard));
 }
 }

@@ -12,7 +12,7 @@ import tempfile
 import numpy as np
 import pytest
 
-from oracle import kmc, philox, sw
+from oracle import kmc, master, philox, sw
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hostshim", "device_logic.cpp")
@@ -35,6 +35,9 @@ def dl():
     L.dl_sw.argtypes = [C.c_int64, dp, dp, dp, dp]
     L.dl_update.argtypes = [C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
                             C.c_int, C.c_uint64, C.c_uint64, C.c_int64, dp]
+    L.dl_master.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                            C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
+                            dp, dp]
     return L
 
 
@@ -102,3 +105,28 @@ def test_update_matches_oracle_step(dl, prob_form):
     assert np.array_equal(out[:, 4] == 1.0, info.jump)
     assert np.abs(out[:, 3] - info.P).max() < 1e-12
     assert np.abs(out[:, :3] - m_new).max() < 1e-9
+
+
+@pytest.mark.parametrize("T,prob_form,static", [(300.0, 0, 0), (300.0, 1, 0), (0.0, 0, 0),
+                                                (300.0, 0, 1)])
+def test_master_step_matches_oracle(dl, T, prob_form, static):
+    """The mean-magnetisation step (weights over two wells, Sec. II.3) against the
+    oracle's master-equation loop: loop record and area to rounding."""
+    rng = np.random.default_rng(11 + prob_form + 2 * static)
+    n = 60
+    axes = rng.normal(size=(n, 3))
+    axes /= np.linalg.norm(axes, axis=1, keepdims=True)
+    axes[:5, 2] = 0.0       # axes in the field plane: degenerate plane at zero field
+    axes[:5] /= np.linalg.norm(axes[:5], axis=1, keepdims=True)
+    S, P, D = 100, 3, 1
+    p = kmc.Params(Ms=4e5, Keff=1.3e4, d=12e-9, T=T, mu0Hmax=0.03, steps_per_period=S,
+                   n_periods=P, n_discard=D, interactions=0, prob_form=prob_form,
+                   dt_override=2e-10 if static else 0.0)
+    dv = kmc.derived(p)
+    H, M, A = master.mean_loop(axes, p)
+    Mg = np.empty((P - D) * S)
+    Ag = np.empty(1)
+    dl.dl_master(n, _p(axes), p.Ms, dv["BK"], dv["beta"], dv["nu0dt"], prob_form,
+                 1 if T > 0 else 0, p.mu0Hmax, S, P, D, static, _p(Mg), _p(Ag))
+    assert np.abs(Mg - M.ravel()).max() < 1e-9 * np.abs(M).max()
+    assert abs(Ag[0] - A) < 1e-9 * max(abs(A), 1.0), (Ag[0], A)

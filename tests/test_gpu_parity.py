@@ -151,6 +151,9 @@ def test_trajectory_config1_fp64(ctx, lib):
     assert np.abs(H - ref.H).max() < 1e-15
     assert abs(res["area"] - ref.area) < 1e-9 * max(abs(ref.area), 1.0)
     assert abs(res["sar"] - ref.sar) < 1e-9 * max(abs(ref.sar), 1.0)
+    # per-particle areas (the per-NP analyses of Sec. III)
+    a_np = a.area_per_np(0)
+    assert np.abs(a_np - ref.area_per_np).max() < 1e-9 * np.abs(ref.area_per_np).max()
 
 
 def test_per_replica_amplitudes_fp64(ctx, lib):
@@ -171,6 +174,9 @@ def test_per_replica_amplitudes_fp64(ctx, lib):
         ref = kmc.simulate(pos, axes, pk, seed=99, stream=r)
         assert np.abs(a.moments(r) - ref.m_final).max() < 1e-9
         assert abs(areas[r] - ref.area) < 1e-9 * max(1.0, abs(ref.area))
+        a_np = a.area_per_np(r)
+        assert np.abs(a_np - ref.area_per_np).max() < 1e-9 * max(1.0, np.abs(ref.area_per_np).max())
+        assert abs(a_np.mean() - areas[r]) < 1e-9 * max(1.0, abs(areas[r]))
         H, M = a.loop(r, 0)
         assert np.abs(H - ref.H).max() < 1e-15
 
@@ -191,3 +197,11 @@ def test_invalid_inputs_rejected(ctx, lib):
     with pytest.raises(lib.MHError) as e:
         a.sar()
     assert e.value.code == lib.ENOTREADY
+    with pytest.raises(lib.MHError) as e:
+        a.area_per_np(0)
+    assert e.value.code == lib.ENOTREADY
+    a.run(2, seed=1)
+    a.sync()
+    with pytest.raises(lib.MHError) as e:
+        a.area_per_np(2)
+    assert e.value.code == -1
