@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c4plain", "c5", "c5wm"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c4plain", "c5", "c5wm", "master"])
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--max-replicas", type=int, default=64)
     ap.add_argument("--assemblies", type=int, default=256)
@@ -81,6 +81,8 @@ def main():
 
     if args.workload == "c3":
         return bench_c3(args, mh, W)
+    if args.workload == "master":
+        return bench_master(args, mh, W)
     if args.workload in ("c5", "c5wm"):
         return bench_c5(args, mh, W)
     if args.workload != "c2":
@@ -167,6 +169,50 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(work)
+    print(json.dumps(line), flush=True)
+
+
+def bench_master(args, mh, W):
+    """Deterministic mean-magnetisation loops (non-interacting particles, the paper's
+    validation method): 10 000 particles with random 3-D axes, 8 axis sets run together,
+    config-2 material at 20 mT, 100 kHz, --periods periods of 2000 steps. One launch per
+    run; value counts particle-steps of the weighted two-well state."""
+    import numpy as np
+    n, sets = 10000, 8
+    axes = np.concatenate([W.axes_random_3d(n, 7000 + q) for q in range(sets)])
+    pos = W.place_lattice_disorder(n, 400e-9, 12e-9, 7100)   # unused without interactions
+    mat = W.Material(mu0Hmax=0.02, n_periods=args.periods, n_discard=min(1, args.periods - 1),
+                     interactions=0)
+    ctx = mh.Context(0)
+    asm = mh.Assembly(ctx, pos, axes, mh.params_from_material(mat, mh.FP64), n_axes_sets=sets)
+    steps_per_run = mat.steps_per_period * mat.n_periods
+
+    def one_run():
+        asm.run_mean_loop(sets)
+        asm.sync()
+        return asm.sar()
+
+    for _ in range(args.warmup):
+        one_run()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = one_run()
+    t1 = time.perf_counter()
+    ctx.set_timing(True)
+    one_run()
+    ms_k, launches = ctx.get_timing(5)
+    ctx.set_timing(False)
+    wall = t1 - t0
+    line = {"metric": "NP·steps/s (mean-magnetisation loop, no interactions)",
+            "value": n * sets * steps_per_run * args.steps / wall, "unit": "NP·steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"mean loop: N={n}, {sets} axis sets, 20 mT, 100 kHz, "
+                                   f"{args.periods} periods x 2000 steps",
+                       "sar_W_per_g": res["sar"] / 1e3, "sar_spread_W_per_g": res["sar_se"] / 1e3},
+            "kernel": {"name": "k_master", "ms_per_launch": ms_k / max(launches, 1),
+                       "launches": launches}}
     print(json.dumps(line), flush=True)
 
 
