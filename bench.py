@@ -64,7 +64,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c4plain", "c5", "c5wm", "master"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4plain", "c5", "c5wm", "master"])
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--max-replicas", type=int, default=64)
     ap.add_argument("--assemblies", type=int, default=256)
@@ -83,6 +83,8 @@ def main():
         return bench_c3(args, mh, W)
     if args.workload == "master":
         return bench_master(args, mh, W)
+    if args.workload == "c1":
+        return bench_c1(args, mh, W)
     if args.workload in ("c5", "c5wm"):
         return bench_c5(args, mh, W)
     if args.workload != "c2":
@@ -169,6 +171,41 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(work)
+    print(json.dumps(line), flush=True)
+
+
+def bench_c1(args, mh, W):
+    """Config 1: N=100 in an 80 nm lysosome, FP64 end to end, 3 periods of 2000 steps.
+    One replica is a chain of 6000 dependent steps in one resident workgroup (latency:
+    us per time step); 1024 replicas on their own Philox streams show the throughput of
+    the same kernel."""
+    a1 = W.config1()
+    ctx = mh.Context(0)
+    asm = mh.Assembly(ctx, a1.pos, a1.axes, mh.params_from_material(a1.mat, mh.FP64))
+    steps_per_run = a1.mat.steps_per_period * a1.mat.n_periods
+    out = {}
+    for R in (1, 1024):
+        for _ in range(args.warmup):
+            asm.run(R, seed=a1.seed)
+            asm.sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            asm.run(R, seed=a1.seed)
+            asm.sync()
+        out[R] = (time.perf_counter() - t0) / args.steps
+    sar = asm.sar()
+    flops = FLOPS_PER_PAIR * a1.n * (a1.n - 1) * 1024 * steps_per_run   # Eq. 1 pair terms
+    line = {"metric": "NP·steps/s (dipolar+kMC)", "value": a1.n * 1024 * steps_per_run / out[1024],
+            "unit": "NP·steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": out[1024] * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "config1: N=100 in an 80 nm lysosome, d=12 nm, 20 mT, 100 kHz, "
+                                   "3 periods x 2000 steps, FP64, 1024 replicas",
+                       "us_per_time_step_one_replica": out[1] / steps_per_run * 1e6,
+                       "sar_W_per_g": sar["sar"] / 1e3, "sar_se_W_per_g": sar["sar_se"] / 1e3},
+            "roofline": {"bound": "alu", "achieved": flops / out[1024] / 1e12, "peak": 78.6,
+                         "unit": "TFLOP/s", "frac": flops / out[1024] / 78.6e12, "traffic": None,
+                         "kernel": "k_resident<double> (whole run, pair terms only)"}}
     print(json.dumps(line), flush=True)
 
 

@@ -216,6 +216,25 @@ int mh_server_poll(mh_server* s, uint64_t req_id, mh_result* out);
 /* Stops after the admitted requests finish (queued ones are dropped) and frees all. */
 int mh_server_destroy(mh_server* s);
 
+/* Launch-shape autotuner. For each particle count in sizes and replica count in
+ * replicas, times the candidate shapes of the tiled field kernel (64 or 16 targets per
+ * block; source split for 2, 3, 4 or 6 blocks per CU) over full 200-step runs of a
+ * synthetic non-overlapping assembly (cubic lattice of spacing 1.25 d, jittered) on
+ * the context's device, and stores the fastest in the context's shape table under the
+ * buckets of (precision, particle count: powers of two from 256, replica groups:
+ * powers of four). Later runs and servers created on the context take their shapes
+ * from the table, else from the built-in rule; results stay bitwise the same alone and
+ * in any batch for a given table. precision: MH_FP64 or MH_FP32_FIELD (the matrix form
+ * has one tile). n_sizes == 0 clears the table. json_path (or NULL) receives the table
+ * as JSON. Synchronous; MH_EINVAL for sizes outside [2, 200000], replicas outside
+ * [1, 4096], more than 64 of either, or an unwritable path. */
+int mh_ctx_autotune(mh_ctx* ctx, int32_t precision, const int64_t* sizes, int32_t n_sizes,
+                    const int64_t* replicas, int32_t n_replicas, const char* json_path);
+
+/* Replace the context's shape table by one written by mh_ctx_autotune. MH_EINVAL (table
+ * unchanged) when the file is missing, empty or not in that format. */
+int mh_ctx_load_shapes(mh_ctx* ctx, const char* json_path);
+
 /* Launch timing (diagnostics for roofline reports). When on, every step-kernel launch
  * is bracketed by a pair of HIP events on the stream it runs on. mh_ctx_get_timing
  * waits for the recorded launches of one kind (0: tiled dipolar-field kernel, 1: resident

@@ -26,6 +26,7 @@ SYMBOLS = [
     "mh_debug_sw", "mh_debug_field", "mh_strerror", "mh_ctx_set_timing", "mh_ctx_get_timing",
     "mh_server_create", "mh_server_submit", "mh_server_poll", "mh_server_destroy",
     "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
+    "mh_ctx_autotune", "mh_ctx_load_shapes",
 ]
 
 
@@ -95,6 +96,9 @@ def _lib():
             "mh_get_moments": ([vp, i64, dp], C.c_int),
             "mh_get_area_per_np": ([vp, i64, dp], C.c_int),
             "mh_run_mean_loop": ([vp, i64, vp], C.c_int),
+            "mh_ctx_autotune": ([vp, i32, C.POINTER(i64), i32, C.POINTER(i64), i32, C.c_char_p],
+                                C.c_int),
+            "mh_ctx_load_shapes": ([vp, C.c_char_p], C.c_int),
             "mh_debug_steps": ([vp, i64, u64, i64, i64, dp, dp], C.c_int),
             "mh_debug_philox": ([vp, u64, u64, i64, u64p, u64p], C.c_int),
             "mh_debug_sw": ([vp, i64, dp, dp, dp, dp], C.c_int),
@@ -160,6 +164,19 @@ class Context:
         _check(_lib().mh_ctx_get_timing(self._h, kind, C.byref(ms), C.byref(cnt)),
                "mh_ctx_get_timing")
         return ms.value, cnt.value
+
+    def autotune(self, precision: int, sizes, replicas=(1,), json_path: str | None = None):
+        """Time the field-kernel launch shapes (mh_ctx_autotune); sizes=() clears."""
+        sz = np.ascontiguousarray(sizes, dtype=np.int64)
+        rp = np.ascontiguousarray(replicas, dtype=np.int64)
+        p64 = C.POINTER(C.c_int64)
+        _check(_lib().mh_ctx_autotune(self._h, precision, sz.ctypes.data_as(p64), sz.shape[0],
+                                      rp.ctypes.data_as(p64), rp.shape[0],
+                                      json_path.encode() if json_path else None),
+               "mh_ctx_autotune")
+
+    def load_shapes(self, json_path: str):
+        _check(_lib().mh_ctx_load_shapes(self._h, json_path.encode()), "mh_ctx_load_shapes")
 
     def debug_philox(self, seed: int, stream: int, ctr: np.ndarray) -> np.ndarray:
         ctr = np.ascontiguousarray(ctr, dtype=np.uint64).reshape(-1, 4)

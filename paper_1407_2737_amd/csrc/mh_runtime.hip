@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <array>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -107,6 +108,17 @@ struct PinBuf {
 
 }  // namespace
 
+// One autotuned launch shape of the tiled field kernel: for assemblies of the given
+// precision class whose particle count and replica-group count fall in the buckets
+// ending at n_max and groups_max, the tile width (0: 64 targets, 1: 16) and the
+// blocks-per-CU target that sets the source split; us is the measured time per step.
+struct ShapeEntry {
+  int fp64;
+  int64_t n_max, groups_max;
+  int tile_kind, bpc;
+  double us;
+};
+
 struct mh_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -123,6 +135,7 @@ struct mh_ctx {
   hipGraphExec_t gexec = nullptr;
   std::vector<uint64_t> gkey;
   int use_graphs = 1;
+  std::vector<ShapeEntry> shapes;  // autotuned shapes (empty: the built-in rule)
 };
 
 struct mh_asm {
@@ -147,6 +160,7 @@ struct mh_asm {
   bool w_built = false;
   int state_parity = 0;  // the current moments live in buffer state_parity
   int64_t k_origin = 0;    // global step of local step 0 (continuous batching)
+  int force_kind = -1, force_bpc = 0;  // autotuner candidates (-1: table or rule)
   std::vector<double> hmax;  // per-replica field amplitudes (replica r uses r mod size)
   uint64_t stream_base = 0;  // Philox stream of replica 0
   hipEvent_t done = nullptr;
@@ -225,23 +239,53 @@ bool wants_resident(const mh_asm* a, int64_t R) {
   return R >= 4 * a->ctx->n_cu && a->n <= (fp64 ? 512 : 1024);
 }
 
-// Field tile width: 64 targets per block once the assembly's own blocks fill the
-// device, else 16 (four times more blocks).
-int tile_kind_for(const mh_asm* a, int64_t R) {
-  const int64_t groups = a->p.precision == MH_FP64 ? R : (R + 3) / 4;
-  return groups * ((a->n + 63) / 64) >= a->ctx->n_cu ? 0 : 1;
+// Buckets of the shape table: particle counts and replica groups (field blocks share
+// the pair geometry across up to four FP32 replicas; FP64 groups are single replicas).
+int64_t n_bucket(int64_t n) {
+  int64_t b = 256;
+  while (b < n && b < ((int64_t)1 << 40)) b *= 2;
+  return b;
+}
+int64_t g_bucket(int64_t g) {
+  int64_t b = 1;
+  while (b < g && b < ((int64_t)1 << 40)) b *= 4;
+  return b;
+}
+int64_t groups_of(const mh_asm* a, int64_t R) {
+  return a->p.precision == MH_FP64 ? R : (R + 3) / 4;
 }
 
-// Source parts per field tile: enough blocks for about three per CU (two run at once,
-// so the last round is partly filled), with parts of at least 1250 sources so that
-// every block keeps enough work to cover its staging and reduction. Measured on one
-// 5000-particle assembly with three replicas and on a batch of 256 assemblies of
-// 200-8000 particles, three per CU beat two, four and six on both.
+// Launch shape of the tiled field kernel: an autotuner candidate, else the context's
+// autotuned entry for the assembly's buckets, else the built-in rule: 64 targets per
+// block once the assembly's own blocks fill the device (else 16, four times more
+// blocks), and a source split for about three blocks per CU. The rule's constants
+// were measured on one 5000-particle assembly with three replicas and on a batch of
+// 256 assemblies of 200-8000 particles (three per CU beat two, four and six on both).
+// Every input is the assembly's own (N, replicas, precision) and the context's
+// table, so an assembly's result does not depend on the batch it runs in.
+struct Shape {
+  int kind, bpc;
+};
+Shape shape_for(const mh_asm* a, int64_t R) {
+  if (a->force_kind >= 0) return Shape{a->force_kind, a->force_bpc};
+  const int64_t groups = groups_of(a, R);
+  const int fp64 = a->p.precision == MH_FP64 ? 1 : 0;
+  const int64_t nb = n_bucket(a->n), gb = g_bucket(groups);
+  for (const ShapeEntry& e : a->ctx->shapes)
+    if (e.fp64 == fp64 && e.n_max == nb && e.groups_max == gb) return Shape{e.tile_kind, e.bpc};
+  return Shape{groups * ((a->n + 63) / 64) >= a->ctx->n_cu ? 0 : 1, 3};
+}
+
+int tile_kind_for(const mh_asm* a, int64_t R) { return shape_for(a, R).kind; }
+
+// Source parts per field tile: enough blocks for the shape's blocks per CU, with parts
+// of at least 1250 sources so that every block keeps enough work to cover its staging
+// and reduction.
 int nsplit_for(const mh_asm* a, int64_t R, int kind) {
-  const int64_t groups = a->p.precision == MH_FP64 ? R : (R + 3) / 4;
+  const int64_t groups = groups_of(a, R);
   const int64_t TI = kind == 0 ? 64 : 16;
   const int64_t blocks = groups * ((a->n + TI - 1) / TI);
-  int64_t sp = (3 * a->ctx->n_cu + blocks - 1) / blocks;
+  int64_t sp = ((int64_t)shape_for(a, R).bpc * a->ctx->n_cu + blocks - 1) / blocks;
   sp = std::min<int64_t>(sp, std::max<int64_t>(1, a->n / 1250));
   return (int)std::max<int64_t>(1, std::min<int64_t>(sp, 16));
 }
@@ -690,6 +734,189 @@ int mh_run_mean_loop(mh_asm* a, int64_t n_replicas, void* hip_stream) {
   if (!a || n_replicas < 1 || n_replicas > 65535) return MH_EINVAL;
   if (a->p.interactions != 0 || !(a->p.Keff > 0)) return MH_EINVAL;
   return run_mean_loop(a, n_replicas, (hipStream_t)hip_stream);
+}
+
+// ---------------------------------------------------------------------------
+// Launch-shape autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+// Synthetic assembly for timing: the n nodes of a cubic lattice (spacing 1.25 d)
+// nearest the centre, each moved by up to 0.1 d (so no pair overlaps), random unit
+// axes; a small linear congruential generator keeps it deterministic.
+void tune_geometry(int64_t n, double d, std::vector<double>& pos, std::vector<double>& axes) {
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  auto uni = [&]() {
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    return (double)(st >> 11) * 0x1.0p-53;
+  };
+  const int m = (int)std::ceil(std::cbrt((double)n)) + 2;
+  std::vector<std::array<double, 4>> nodes;
+  for (int x = -m; x <= m; ++x)
+    for (int y = -m; y <= m; ++y)
+      for (int z = -m; z <= m; ++z)
+        nodes.push_back({(double)x, (double)y, (double)z, (double)(x * x + y * y + z * z)});
+  std::stable_sort(nodes.begin(), nodes.end(),
+                   [](const std::array<double, 4>& a, const std::array<double, 4>& b) {
+                     return a[3] < b[3];
+                   });
+  pos.resize(3 * n);
+  axes.resize(3 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int c = 0; c < 3; ++c) pos[3 * i + c] = d * (1.25 * nodes[i][c] + 0.1 * (2.0 * uni() - 1.0) / std::sqrt(3.0));
+    double v[3], r2 = 0.0;
+    do {
+      r2 = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        v[c] = 2.0 * uni() - 1.0;
+        r2 += v[c] * v[c];
+      }
+    } while (r2 > 1.0 || r2 < 1e-6);
+    for (int c = 0; c < 3; ++c) axes[3 * i + c] = v[c] / std::sqrt(r2);
+  }
+}
+
+// Seconds per time step of one run of `a` with R replicas (best of `reps`, after a
+// warm-up run that absorbs allocation and graph capture).
+double time_run(mh_asm* a, int64_t R, int reps) {
+  mh_ctx* c = a->ctx;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1.0;
+  double best = -1.0;
+  for (int q = 0; q <= reps; ++q) {
+    if (hipEventRecord(e0, c->stream) != hipSuccess || mh_run_loops(a, R, 12345, nullptr) ||
+        hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      best = -1.0;
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double sec = ms * 1e-3 / (double)total_steps(a->p);
+    if (q > 0 && (best < 0 || sec < best)) best = sec;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+}  // namespace
+
+int mh_ctx_autotune(mh_ctx* c, int32_t precision, const int64_t* sizes, int32_t n_sizes,
+                    const int64_t* replicas, int32_t n_replicas, const char* json_path) {
+  if (!c) return MH_EINVAL;
+  if (n_sizes == 0) {  // clear: back to the built-in rule
+    c->shapes.clear();
+    return MH_OK;
+  }
+  if (!sizes || n_sizes < 0 || !replicas || n_replicas < 1 || n_replicas > 64 || n_sizes > 64 ||
+      (precision != MH_FP64 && precision != MH_FP32_FIELD))
+    return MH_EINVAL;
+  for (int q = 0; q < n_sizes; ++q)
+    if (sizes[q] < 2 || sizes[q] > 200000) return MH_EINVAL;
+  for (int q = 0; q < n_replicas; ++q)
+    if (replicas[q] < 1 || replicas[q] > 4096) return MH_EINVAL;
+  if (set_dev(c)) return MH_EDEVICE;
+  mh_params p{};
+  p.Ms = 4e5;
+  p.Keff = 1.3e4;
+  p.d = 1e-8;
+  p.T = 300.0;
+  p.tau0 = 1e-10;
+  p.rho = 5200.0;
+  p.f = 1e5;
+  p.mu0Hmax = 0.02;
+  p.steps_per_period = 100;
+  p.n_periods = 2;
+  p.n_discard = 1;
+  p.prob_form = MH_P_TWO_STATE;
+  p.precision = precision;
+  p.interactions = 1;
+  const int kinds[2] = {0, 1};
+  const int bpcs[4] = {2, 3, 4, 6};
+  for (int qs = 0; qs < n_sizes; ++qs) {
+    std::vector<double> pos, axes;
+    tune_geometry(sizes[qs], p.d, pos, axes);
+    mh_asm* a = nullptr;
+    int e = mh_create_assembly(c, sizes[qs], pos.data(), axes.data(), 1, &p, &a);
+    if (e) return e;
+    for (int qr = 0; qr < n_replicas; ++qr) {
+      const int64_t R = replicas[qr];
+      if (wants_resident(a, R)) continue;  // one workgroup per replica: no tile shape
+      ShapeEntry best{precision == MH_FP64 ? 1 : 0, n_bucket(a->n), g_bucket(groups_of(a, R)),
+                      -1, 0, 0.0};
+      for (int kind : kinds)
+        for (int bpc : bpcs) {
+          a->force_kind = kind;
+          a->force_bpc = bpc;
+          const double sec = time_run(a, R, 2);
+          if (sec < 0) {
+            mh_destroy_assembly(a);
+            return MH_EDEVICE;
+          }
+          if (best.tile_kind < 0 || sec * 1e6 < best.us) {
+            best.tile_kind = kind;
+            best.bpc = bpc;
+            best.us = sec * 1e6;
+          }
+        }
+      a->force_kind = -1;
+      bool replaced = false;
+      for (ShapeEntry& x : c->shapes)
+        if (x.fp64 == best.fp64 && x.n_max == best.n_max && x.groups_max == best.groups_max) {
+          x = best;
+          replaced = true;
+        }
+      if (!replaced) c->shapes.push_back(best);
+    }
+    mh_destroy_assembly(a);
+  }
+  if (json_path) {
+    FILE* f = std::fopen(json_path, "w");
+    if (!f) return MH_EINVAL;
+    std::fprintf(f, "[\n");
+    for (size_t q = 0; q < c->shapes.size(); ++q) {
+      const ShapeEntry& x = c->shapes[q];
+      std::fprintf(f,
+                   "  {\"fp64\": %d, \"n_max\": %lld, \"groups_max\": %lld, \"tile_kind\": %d, "
+                   "\"blocks_per_cu\": %d, \"us_per_step\": %.3f}%s\n",
+                   x.fp64, (long long)x.n_max, (long long)x.groups_max, x.tile_kind, x.bpc, x.us,
+                   q + 1 < c->shapes.size() ? "," : "");
+    }
+    std::fprintf(f, "]\n");
+    if (std::fclose(f) != 0) return MH_EINVAL;
+  }
+  return MH_OK;
+}
+
+int mh_ctx_load_shapes(mh_ctx* c, const char* json_path) {
+  if (!c || !json_path) return MH_EINVAL;
+  FILE* f = std::fopen(json_path, "r");
+  if (!f) return MH_EINVAL;
+  std::vector<ShapeEntry> v;
+  char line[512];
+  int bad = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    const char* b = std::strchr(line, '{');
+    if (!b) continue;
+    ShapeEntry x{};
+    long long nm = 0, gm = 0;
+    if (std::sscanf(b,
+                    " {\"fp64\": %d, \"n_max\": %lld, \"groups_max\": %lld, \"tile_kind\": %d, "
+                    "\"blocks_per_cu\": %d, \"us_per_step\": %lf",
+                    &x.fp64, &nm, &gm, &x.tile_kind, &x.bpc, &x.us) != 6 ||
+        (x.fp64 != 0 && x.fp64 != 1) || nm < 256 || gm < 1 || nm != n_bucket(nm) ||
+        gm != g_bucket(gm) || (x.tile_kind != 0 && x.tile_kind != 1) || x.bpc < 1 || x.bpc > 64) {
+      bad = 1;
+      break;
+    }
+    x.n_max = nm;
+    x.groups_max = gm;
+    v.push_back(x);
+  }
+  std::fclose(f);
+  if (bad || v.empty()) return MH_EINVAL;
+  c->shapes = v;
+  return MH_OK;
 }
 
 int mh_ctx_set_timing(mh_ctx* c, int on) {
@@ -1327,6 +1554,7 @@ int mh_server_create(mh_ctx* ctx, size_t hbm_budget_bytes, mh_server** out) {
     return e;
   }
   s->budget = hbm_budget_bytes;
+  s->ctx->shapes = ctx->shapes;  // requests run with the launch shapes of the caller's context
   s->th = std::thread([s] { s->loop(); });
   *out = s;
   return MH_OK;
