@@ -20,6 +20,10 @@ Readings of points the paper leaves open (applied identically by the GPU library
 * T = 0: steps vi-vii are skipped; K_eff = 0: the moment aligns with B_tot.
 * Area: A = M_S sum_k mu0H_k (m_x,k - m_x,k-1) over the kept steps (work done at
   constant field per step), J/m^3; SAR = A f / rho.
+* Eq. 6: the dipolar field "at +mu0 H_max" (-mu0 H_max) is the x component of the Eq. 1
+  field acting in the step whose applied field is +H_max (-H_max), k = 0 (S/2) mod S,
+  i.e. computed from that step's start-of-step moments; Delta-_Hdip per particle is
+  its difference, averaged over the kept periods.
 """
 from __future__ import annotations
 
@@ -147,6 +151,7 @@ class StepInfo:
     u: np.ndarray
     jump: np.ndarray
     u2: np.ndarray | None = None
+    Bdip: np.ndarray | None = None   # the Eq. 1 part of B (zeros without interactions)
 
 
 def step(pos, axes, m, k, p: Params, seed: int, stream: int, B_override=None):
@@ -155,19 +160,21 @@ def step(pos, axes, m, k, p: Params, seed: int, stream: int, B_override=None):
     dv = derived(p)
     n = pos.shape[0]
     Bx = applied_field(k, p)
+    Bdip = None
     if B_override is not None:
         B = np.array(B_override, dtype=np.float64)
     else:
         B = np.zeros((n, 3))
         if p.interactions and n > 1:
             B += dipolar_field(pos, m, dv["C"])
+        Bdip = B.copy()
         B[:, 0] += Bx
     if p.Keff <= 0:
         Bn = np.linalg.norm(B, axis=1)
         m_new = np.where(Bn[:, None] > 0, B / np.where(Bn > 0, Bn, 1.0)[:, None], m)
         z = np.zeros(n)
         return m_new, StepInfo(B, z, z, z, z, z, z, z, z, np.zeros(n, bool), z, z,
-                               np.zeros(n, bool))
+                               np.zeros(n, bool), None, Bdip)
     u2, hx, hy, theta0 = working_plane(B, axes, m, dv["BK"])
     theta, is_min, count = sw.stationary_points(hx, hy)
     th_c, e_c, th_o, e_o, e3, two = sw.classify(theta0, theta, is_min, count, hx, hy)
@@ -185,7 +192,7 @@ def step(pos, axes, m, k, p: Params, seed: int, stream: int, B_override=None):
         jump = two & (u < P)
         th_new = np.where(jump, th_o, th_c)
     m_new = np.cos(th_new)[:, None] * axes + np.sin(th_new)[:, None] * u2
-    info = StepInfo(B, hx, hy, theta0, th_c, th_o, e_c, e_o, e3, two, P, u, jump, u2)
+    info = StepInfo(B, hx, hy, theta0, th_c, th_o, e_c, e_o, e3, two, P, u, jump, u2, Bdip)
     return m_new, info
 
 
@@ -204,6 +211,7 @@ class LoopResult:
     m_final: np.ndarray
     jumps: int = 0
     trace: list = field(default_factory=list)
+    dhdip_per_np: np.ndarray | None = None   # (N,) Eq. 6, T, mean over kept periods
 
 
 def simulate(pos, axes, p: Params, seed: int, stream: int = 0, n_steps: int | None = None,
@@ -216,6 +224,7 @@ def simulate(pos, axes, p: Params, seed: int, stream: int = 0, n_steps: int | No
     m = initial_moments(axes) if m0 is None else np.array(m0, dtype=np.float64)
     n = pos.shape[0]
     area = np.zeros(n)
+    dhdip = np.zeros(n)
     Mrec = np.zeros((max(n_kept, 1), S))
     Hrec = np.array([applied_field(k, p) for k in range(S)])
     jumps = 0
@@ -223,6 +232,9 @@ def simulate(pos, axes, p: Params, seed: int, stream: int = 0, n_steps: int | No
     for k in range(total):
         m_new, info = step(pos, axes, m, k, p, seed, stream)
         jumps += int(info.jump.sum())
+        if k >= kept0 and info.Bdip is not None and k % S in (0, S // 2):
+            # Eq. 6: dipolar field along x at +H_max minus at -H_max
+            dhdip += info.Bdip[:, 0] if k % S == 0 else -info.Bdip[:, 0]
         if k >= kept0:
             area += p.Ms * applied_field(k, p) * (m_new[:, 0] - m[:, 0])
             Mrec[(k - kept0) // S, k % S] = p.Ms * m_new[:, 0].mean()
@@ -231,7 +243,8 @@ def simulate(pos, axes, p: Params, seed: int, stream: int = 0, n_steps: int | No
         m = m_new
     area_np = area / max(n_kept, 1)
     A = float(area_np.mean()) if n else 0.0
-    return LoopResult(Hrec, Mrec[:n_kept], area_np, A, A * p.f / p.rho, m, jumps, trace)
+    return LoopResult(Hrec, Mrec[:n_kept], area_np, A, A * p.f / p.rho, m, jumps, trace,
+                      dhdip / max(n_kept, 1))
 
 
 def sar_from_area(area, f, rho=5200.0):
