@@ -148,6 +148,20 @@ int mh_get_replica_areas(mh_asm* a, double* area);
  * any run. */
 int mh_get_area_per_np(mh_asm* a, int64_t replica, double* area_per_np);
 
+/* Eq. 6 per particle of one replica (n values, tesla): the x component of the dipolar
+ * field acting in the +mu0 Hmax step (k = 0 mod S, from that step's start-of-step
+ * moments) minus that in the -mu0 Hmax step (k = S/2 mod S), averaged over the kept
+ * periods; positive where the neighbours' field reinforces the applied one (Sec.
+ * III.3). Zero without interactions and after mh_run_mean_loop. MH_EINVAL for a
+ * replica outside the last run, MH_ENOTREADY before any run. */
+int mh_get_dhdip(mh_asm* a, int64_t replica, double* dhdip_T);
+
+/* Local volume concentration of Eq. 8 (Sec. III.5) for every particle (n values):
+ * phi_N = 3 N V / (4 pi r_N^3) = N d^3 / (8 r_N^3), with r_N the exact distance to the
+ * particle's N-th nearest neighbour. Geometry only (no run needed); synchronous.
+ * MH_EINVAL unless 1 <= N <= n - 1. */
+int mh_get_local_concentration(mh_asm* a, int32_t N, double* phi);
+
 /* Current moments of one replica (n x 3). */
 int mh_get_moments(mh_asm* a, int64_t replica, double* m);
 

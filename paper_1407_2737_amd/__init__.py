@@ -26,7 +26,8 @@ SYMBOLS = [
     "mh_debug_sw", "mh_debug_field", "mh_strerror", "mh_ctx_set_timing", "mh_ctx_get_timing",
     "mh_server_create", "mh_server_submit", "mh_server_poll", "mh_server_destroy",
     "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
-    "mh_ctx_autotune", "mh_ctx_load_shapes",
+    "mh_ctx_autotune", "mh_ctx_load_shapes", "mh_get_dhdip",
+    "mh_get_local_concentration",
 ]
 
 
@@ -95,6 +96,8 @@ def _lib():
             "mh_get_replica_areas": ([vp, dp], C.c_int),
             "mh_get_moments": ([vp, i64, dp], C.c_int),
             "mh_get_area_per_np": ([vp, i64, dp], C.c_int),
+            "mh_get_dhdip": ([vp, i64, dp], C.c_int),
+            "mh_get_local_concentration": ([vp, i32, dp], C.c_int),
             "mh_run_mean_loop": ([vp, i64, vp], C.c_int),
             "mh_ctx_autotune": ([vp, i32, C.POINTER(i64), i32, C.POINTER(i64), i32, C.c_char_p],
                                 C.c_int),
@@ -263,6 +266,19 @@ class Assembly:
         """Per-particle loop areas of one replica, J/m^3 (mean over kept periods)."""
         out = np.empty(self.n)
         _check(_lib().mh_get_area_per_np(self._h, replica, _dp(out)), "mh_get_area_per_np")
+        return out
+
+    def local_concentration(self, N: int = 20) -> np.ndarray:
+        """Eq. 8 phi_N of every particle."""
+        out = np.empty(self.n)
+        _check(_lib().mh_get_local_concentration(self._h, N, _dp(out)),
+               "mh_get_local_concentration")
+        return out
+
+    def dhdip(self, replica: int = 0) -> np.ndarray:
+        """Eq. 6 per particle of one replica, tesla (mean over kept periods)."""
+        out = np.empty(self.n)
+        _check(_lib().mh_get_dhdip(self._h, replica, _dp(out)), "mh_get_dhdip")
         return out
 
     def moments(self, replica: int = 0) -> np.ndarray:

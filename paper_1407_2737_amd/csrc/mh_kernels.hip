@@ -473,6 +473,51 @@ __global__ __launch_bounds__(256) void k_master(const SysDesc* __restrict__ syst
   }
 }
 
+// Local volume concentration, Eq. 8: phi_N = N / (8 (r_N/d)^3) with r_N the distance
+// to the N-th nearest other particle (positions in units of d). The N-th smallest
+// squared distance is found exactly by bisection on its bit pattern (non-negative
+// doubles order like their bits): 64 passes, each counting the squared distances at
+// or below the candidate over positions staged through LDS, keep the smallest value
+// with at least N of them. Squared distances are dx*dx + dy*dy + dz*dz.
+__global__ __launch_bounds__(256) void k_local_conc(const D4* __restrict__ pos, int n, int N,
+                                                    double* __restrict__ phi) {
+  __shared__ double sx[1024], sy[1024], sz[1024];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const D4 pi = pos[i < n ? i : n - 1];
+  uint64_t lo = 0, hi = 0x7FF0000000000000ull;  // +0 .. +inf
+  for (int pass = 0; pass < 64; ++pass) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    const double t = __longlong_as_double((long long)mid);
+    int cnt = 0;
+    for (int c0 = 0; c0 < n; c0 += 1024) {
+      const int cn = min(1024, n - c0);
+      __syncthreads();
+      for (int j = threadIdx.x; j < cn; j += 256) {
+        const D4 p = pos[c0 + j];
+        sx[j] = p.x;
+        sy[j] = p.y;
+        sz[j] = p.z;
+      }
+      __syncthreads();
+      for (int j = 0; j < cn; ++j) {
+        const double dx = sx[j] - pi.x, dy = sy[j] - pi.y, dz = sz[j] - pi.z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        cnt += (c0 + j != i && d2 <= t) ? 1 : 0;
+      }
+    }
+    if (lo < hi) {
+      if (cnt >= N)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+  }
+  if (i < n) {
+    const double r = sqrt(__longlong_as_double((long long)lo));
+    phi[i] = (double)N / (8.0 * r * r * r);
+  }
+}
+
 // Start of a run: m_i = sign(n_i . x) n_i in buffer 0 (both precisions), zero the
 // area accumulators and the loop-record partials.
 __global__ void k_init(const SysDesc* __restrict__ systems) {
@@ -497,6 +542,7 @@ __global__ void k_init(const SysDesc* __restrict__ systems) {
     }
     s.area[i] = 0.0;
     s.area[s.n + i] = 0.0;
+    if (s.dhdip) s.dhdip[i] = 0.0;
   }
   const int64_t rows = (int64_t)(s.total_steps - s.kept0) * s.ntiles;
   for (int64_t r = i; r < rows; r += (int64_t)gridDim.x * blockDim.x) s.recpart[r] = 0.0;
@@ -635,6 +681,11 @@ hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st) 
 hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st) {
   if (nsys == 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize_sys, dim3(nsys), dim3(256), 0, st, d_sys);
+  return hipGetLastError();
+}
+
+hipError_t launch_local_conc(const D4* pos, int n, int N, double* phi, hipStream_t st) {
+  hipLaunchKernelGGL(k_local_conc, dim3((n + 255) / 256), dim3(256), 0, st, pos, n, N, phi);
   return hipGetLastError();
 }
 

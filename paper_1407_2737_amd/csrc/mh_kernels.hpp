@@ -27,6 +27,7 @@ struct SysDesc {
   D4* field;         // reduced dipolar sums, nsplit partial sums per particle ([part][n])
   double* rec;       // loop record of the kept steps: sum_i m_x after each step
   double* sys_area;  // this system's loop area (J/m^3), written at the end of a run
+  double* dhdip;     // per-particle Eq. 6 sums over kept periods (T), or null
   int64_t stride;    // distance between the two moment buffers (elements)
   int64_t k_origin;  // global step at which this system's step 0 runs
   uint64_t seed, stream;
@@ -72,6 +73,15 @@ __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur
   }
   const double Bext = applied_field(s, k);
   const double Bx = Bext + s.Bscale * ax, By = s.Bscale * ay, Bz = s.Bscale * az;
+  if (s.dhdip && k >= s.kept0) {
+    // Eq. 6: the dipolar field along x in the +Hmax step (k = 0 mod S) minus that in
+    // the -Hmax step (k = S/2 mod S)
+    const int64_t ph = k % s.S;
+    if (ph == 0)
+      s.dhdip[i] += s.Bscale * ax;
+    else if (ph == s.S / 2)
+      s.dhdip[i] -= s.Bscale * ax;
+  }
   const D4 mo = s.m64[(int64_t)cur * s.stride + i];
   const D4 nn = s.axes[i];
   const NPResult r =

@@ -46,6 +46,7 @@ hipError_t launch_wm_pack(const SysDesc* d_sys, int R, int n, const WMArgs& g, i
 hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st);
 hipError_t launch_init(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st);
 hipError_t launch_master(const SysDesc* d_sys, int nsys, int nmax, hipStream_t st);
+hipError_t launch_local_conc(const D4* pos, int n, int N, double* phi, hipStream_t st);
 hipError_t launch_sync32(const SysDesc* d_sys, int nsys, int nmax, int b, hipStream_t st);
 hipError_t launch_finalize_asm(const double* d_sys_area, int R, double* d_out, hipStream_t st);
 hipError_t launch_area_per_np(const double* d_area, int n, int R, int n_kept, double* d_out,
@@ -153,7 +154,7 @@ struct mh_asm {
   int resident = 0;
   int tile_kind = 0;  // 0: 64 targets per block, 1: 16
   int nsplit = 1;     // source parts per field tile
-  DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp, field;
+  DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp, field, dhdip;
   // interaction-matrix form: W hi/lo (Mp x Kp), M^T hi/lo (Rp x Kp), B^T (Rp x Mp)
   DevBuf whi, wlo, mhi, mlo, bt;
   int Mp = 0, Kp = 0, Rp = 0;
@@ -302,6 +303,7 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   if ((e = a->m64.ensure(sizeof(D4) * 2 * R * n))) return e;
   if (a->p.precision == MH_FP32_FIELD && (e = a->m32.ensure(sizeof(F4) * 2 * R * n))) return e;
   if ((e = a->area.ensure(sizeof(double) * 2 * R * n))) return e;
+  if ((e = a->dhdip.ensure(sizeof(double) * R * n))) return e;
   if ((e = a->recpart.ensure(sizeof(double) * R * rows * a->ntiles + 8))) return e;
   if ((e = a->rec.ensure(sizeof(double) * R * rows + 8))) return e;
   if ((e = a->sys_area.ensure(sizeof(double) * R))) return e;
@@ -357,6 +359,7 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.field = a->resident ? nullptr : a->field.as<D4>() + r * n * a->nsplit;
   s.nsplit = a->nsplit;
   s.sys_area = a->sys_area.as<double>() + r;
+  s.dhdip = a->dhdip.as<double>() + r * n;
   s.diag = nullptr;
   s.stride = a->R * n;
   s.seed = a->seed;
@@ -686,7 +689,8 @@ int run_mean_loop(mh_asm* a, int64_t R, hipStream_t st) {
   const int64_t n = a->n;
   const int64_t rows = (int64_t)n_kept(a->p) * a->p.steps_per_period;
   int e;
-  if ((e = a->m64.ensure(sizeof(D4) * 2 * R * n)) || (e = a->area.ensure(sizeof(double) * 2 * R * n)))
+  if ((e = a->m64.ensure(sizeof(D4) * 2 * R * n)) || (e = a->area.ensure(sizeof(double) * 2 * R * n)) ||
+      (e = a->dhdip.ensure(sizeof(double) * R * n)))
     return e;
   a->resident = 0;
   a->nsplit = 1;
@@ -1052,7 +1056,7 @@ int mh_destroy_assembly(mh_asm* a) {
     (void)hipEventSynchronize(a->done);
     (void)hipEventDestroy(a->done);
   }
-  DevBuf* bufs[] = {&a->pos64, &a->pos32, &a->axes, &a->m64, &a->m32, &a->area, &a->recpart,
+  DevBuf* bufs[] = {&a->pos64, &a->pos32, &a->axes, &a->m64, &a->m32, &a->area, &a->dhdip, &a->recpart,
                     &a->rec, &a->sys_area, &a->stats, &a->diag, &a->tmp, &a->field,
                     &a->whi, &a->wlo, &a->mhi, &a->mlo, &a->bt};
   for (auto* b : bufs) b->release();
@@ -1172,6 +1176,32 @@ int mh_get_area_per_np(mh_asm* a, int64_t replica, double* area_per_np) {
                      a->ctx->stream) != hipSuccess ||
       hipStreamSynchronize(a->ctx->stream) != hipSuccess)
     return MH_EDEVICE;
+  return MH_OK;
+}
+
+int mh_get_local_concentration(mh_asm* a, int32_t N, double* phi) {
+  if (!a || !phi || N < 1 || N > a->n - 1) return MH_EINVAL;
+  if (set_dev(a->ctx)) return MH_EDEVICE;
+  int e;
+  if ((e = a->tmp.ensure(sizeof(double) * a->n))) return e;
+  hipStream_t st = a->ctx->stream;
+  if (launch_local_conc(a->pos64.as<D4>(), (int)a->n, N, a->tmp.as<double>(), st) != hipSuccess ||
+      hipMemcpyAsync(phi, a->tmp.p, sizeof(double) * a->n, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return MH_EDEVICE;
+  return MH_OK;
+}
+
+int mh_get_dhdip(mh_asm* a, int64_t replica, double* dhdip_T) {
+  if (!a || !dhdip_T) return MH_EINVAL;
+  int e = mh_sync(a);
+  if (e) return e;
+  if (replica < 0 || replica >= a->R) return MH_EINVAL;
+  if (hipMemcpy(dhdip_T, a->dhdip.as<double>() + replica * a->n, sizeof(double) * a->n,
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return MH_EDEVICE;
+  const int nk = n_kept(a->p);
+  for (int64_t i = 0; i < a->n; ++i) dhdip_T[i] = nk > 0 ? dhdip_T[i] / nk : 0.0;
   return MH_OK;
 }
 
@@ -1366,7 +1396,7 @@ struct SReq {
 size_t request_bytes(int64_t n, const mh_params& p, int64_t R, int64_t maxR) {
   const int64_t rows = (int64_t)(p.n_periods - p.n_discard) * p.steps_per_period;
   const int64_t nt = (n + 255) / 256;
-  size_t b = (size_t)R * n * (2 * 32 + 2 * 16 + 16 + 32) + (size_t)R * rows * (nt + 1) * 8;
+  size_t b = (size_t)R * n * (2 * 32 + 2 * 16 + 16 + 8 + 32) + (size_t)R * rows * (nt + 1) * 8;
   b += (size_t)n * (32 + 16 + 32) + (size_t)maxR * 8 + 4096;
   if (p.precision == MH_BF16X3_WM) {
     const int64_t rq = 8 * 192;

@@ -1,0 +1,94 @@
+"""The paper's per-particle analyses on the GPU, through the C-ABI: Eq. 6 (Delta-_Hdip)
+and Eq. 8 (local concentration phi_N), against the oracle and closed forms."""
+import numpy as np
+import pytest
+
+from oracle import analysis, kmc
+from paper_1407_2737_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+D = 12e-9
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+@pytest.mark.parametrize("N", [1, 5, 20, 200])
+def test_local_concentration_matches_oracle(ctx, lib, N):
+    n = 700
+    pos = W.place_random(n, 0.5 * D * (n / 0.1) ** (1 / 3), D, 81)
+    axes = W.axes_random_3d(n, 82)
+    a = lib.Assembly(ctx, pos, axes, lib.Params.make(lib.FP32_FIELD))
+    got = a.local_concentration(N)
+    ref = analysis.local_concentration(pos, D, N)
+    assert np.abs(got / ref - 1).max() < 1e-12
+    a.close()
+
+
+def test_local_concentration_lattice_and_errors(ctx, lib):
+    a_l = 1.5 * D
+    g = np.arange(-2, 3) * a_l
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    axes = W.axes_random_3d(pos.shape[0], 3)
+    a = lib.Assembly(ctx, pos, axes, lib.Params.make(lib.FP64))
+    c = np.argmin(np.linalg.norm(pos, axis=1))
+    for N, shell in ((6, 1.0), (18, 2 ** 0.5), (26, 3 ** 0.5)):
+        assert a.local_concentration(N)[c] == pytest.approx(N * D ** 3 / (8 * (shell * a_l) ** 3),
+                                                             rel=1e-13)
+    for N in (0, pos.shape[0]):
+        with pytest.raises(lib.MHError) as e:
+            a.local_concentration(N)
+        assert e.value.code == -1
+    with pytest.raises(lib.MHError) as e:
+        a.dhdip(0)
+    assert e.value.code == lib.ENOTREADY
+    a.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-6), (2, 1e-4)])
+def test_dhdip_pair_closed_form(ctx, lib, prec, tol):
+    """Contact pair along the field, axes along x, 1 T against mu0 H_K = 5 mT at T = 0:
+    Delta-_Hdip = mu0 M_S / 6 for both particles, in every field form."""
+    pos = np.array([[0.0, 0, 0], [D, 0, 0]])
+    axes = np.tile([1.0, 0, 0], (2, 1))
+    p = lib.Params.make(prec, Ms=4e5, Keff=1e3, d=D, T=0.0, mu0Hmax=1.0, steps_per_period=8,
+                        n_periods=3, n_discard=1)
+    a = lib.Assembly(ctx, pos, axes, p)
+    a.run(2, seed=1)
+    a.sync()
+    want = kmc.MU0 * 4e5 / 6
+    for r in range(2):
+        assert np.abs(a.dhdip(r) / want - 1).max() < tol
+    a.close()
+
+
+def test_dhdip_trajectory_and_amplitudes(ctx, lib):
+    """FP64 runs follow the oracle, so Eq. 6 per particle agrees to rounding: config 1
+    and three replicas at their own amplitudes."""
+    a1 = W.config1()
+    pk = kmc.Params.from_dict(a1.mat.as_dict())
+    a = lib.Assembly(ctx, a1.pos, a1.axes, lib.params_from_material(a1.mat, lib.FP64))
+    a.run(1, seed=a1.seed)
+    a.sync()
+    ref = kmc.simulate(a1.pos, a1.axes, pk, seed=a1.seed, stream=0)
+    got = a.dhdip(0)
+    print(f"config 1 mean Delta-_Hdip {got.mean() * 1e3:.4f} mT (oracle {ref.dhdip_per_np.mean() * 1e3:.4f})")
+    assert np.abs(got - ref.dhdip_per_np).max() < 1e-9 * np.abs(ref.dhdip_per_np).max()
+    a.close()
+    n = 60
+    pos = W.place_random(n, 70e-9, D, 71)
+    axes = W.axes_random_3d(n, 72)
+    amps = [0.01, 0.02, 0.04]
+    kw = dict(steps_per_period=100, n_periods=2, n_discard=1)
+    a = lib.Assembly(ctx, pos, axes, lib.Params.make(lib.FP64, **kw))
+    a.set_replica_fields(amps)
+    a.run(3, seed=99)
+    a.sync()
+    for r, h in enumerate(amps):
+        ref = kmc.simulate(pos, axes, kmc.Params(mu0Hmax=h, **kw), seed=99, stream=r)
+        assert np.abs(a.dhdip(r) - ref.dhdip_per_np).max() < 1e-9 * np.abs(ref.dhdip_per_np).max()
+    a.close()
