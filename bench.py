@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="config 3: built-in launch-shape rule")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4plain", "c5", "c5wm", "master"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4plain", "c5", "c5wm", "master", "sweep"])
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--max-replicas", type=int, default=64)
     ap.add_argument("--assemblies", type=int, default=256)
@@ -86,6 +86,8 @@ def main():
         return bench_master(args, mh, W)
     if args.workload == "c1":
         return bench_c1(args, mh, W)
+    if args.workload == "sweep":
+        return bench_sweep(args, mh, W)
     if args.workload in ("c5", "c5wm"):
         return bench_c5(args, mh, W)
     if args.workload != "c2":
@@ -142,10 +144,17 @@ def main():
     depth = 1.0 - np.linalg.norm(w2.pos, axis=1) / w2.radius
     edges = [0.0, 0.05, 0.1, 0.2, 0.3, 0.5, 1.0]
     which = np.digitize(depth, edges[1:-1])
-    profile = {}
+    profile, dh_profile, corr = {}, {}, {}
     for r, h in enumerate(amps):
         a_np = asm.area_per_np(r)
-        profile[f"{h * 1e3:g} mT"] = [float(a_np[which == b].mean()) for b in range(len(edges) - 1)]
+        dh = asm.dhdip(r)                     # Eq. 6 per particle
+        key = f"{h * 1e3:g} mT"
+        profile[key] = [float(a_np[which == b].mean()) for b in range(len(edges) - 1)]
+        dh_profile[key] = [float(dh[which == b].mean() * 1e3) for b in range(len(edges) - 1)]
+        corr[key] = float(np.corrcoef(dh, a_np)[0, 1])
+    phi20 = asm.local_concentration(20)      # Eq. 8
+    analyses = {"dhdip_mT_vs_depth": dh_profile, "corr_dhdip_area": corr,
+                "phi20_vs_depth": [float(phi20[which == b].mean()) for b in range(len(edges) - 1)]}
     line = {
         "metric": "NP·steps/s (dipolar+kMC)",
         "value": value,
@@ -167,7 +176,8 @@ def main():
                    "area_Jm3_vs_depth": {"depth_edges": edges,
                                          "count": [int((which == b).sum())
                                                    for b in range(len(edges) - 1)],
-                                         **profile}},
+                                         **profile},
+                   "per_particle_analyses": analyses},
         "roofline": roofline,
     }
     if not args.no_cpu:
@@ -207,6 +217,55 @@ def bench_c1(args, mh, W):
             "roofline": {"bound": "alu", "achieved": flops / out[1024] / 1e12, "peak": 78.6,
                          "unit": "TFLOP/s", "frac": flops / out[1024] / 78.6e12, "traffic": None,
                          "kernel": "k_resident<double> (whole run, pair terms only)"}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_sweep(args, mh, W):
+    """Concentration sweep of large particles (Sec. III.2-3, the d -> infinity case): 3000
+    particles on a maximally disordered cubic lattice, random 3-D axes (8 axis sets as
+    replicas), Ms = 1e6 A/m, K = 1.3e4 J/m^3, T = 0, 40 mT, 100 kHz, 2 periods of 2000
+    steps (first discarded), volume fractions 0.01-30 %, all assemblies in one batch.
+    Reports the dimensionless area A/K against the dimensionless concentration
+    mu0 Ms^2 phi / K."""
+    import numpy as np
+    n, sets, d = 3000, 8, 20e-9
+    phis = [1e-4, 1e-3, 3e-3, 1e-2, 3e-2, 0.1, 0.3]
+    Ms, K = 1e6, 1.3e4
+    ctx = mh.Context(0)
+    asms = []
+    for q, phi in enumerate(phis):
+        radius = 0.5 * d * (n / phi) ** (1.0 / 3.0)
+        pos = W.place_lattice_disorder(n, radius, d, 8000 + q)
+        axes = np.concatenate([W.axes_random_3d(n, 8100 + 10 * q + s_) for s_ in range(sets)])
+        mat = W.Material(Ms=Ms, Keff=K, d=d, T=0.0, mu0Hmax=0.04, n_periods=2, n_discard=1)
+        asms.append(mh.Assembly(ctx, pos, axes, mh.params_from_material(mat, mh.FP32_FIELD),
+                                n_axes_sets=sets))
+    steps_per_run = 2 * 2000
+
+    def one_run():
+        mh.run_batch(asms, [sets] * len(asms), [9000 + q for q in range(len(asms))])
+        for a in asms:
+            a.sync()
+        return [a.sar() for a in asms]
+
+    for _ in range(args.warmup):
+        one_run()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = one_run()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    mu0 = 4e-7 * np.pi
+    curve = [{"phi": phi, "mu0_Ms2_phi_over_K": mu0 * Ms ** 2 * phi / K,
+              "A_over_K": r["area"] / K, "se": r["area_se"] / K} for phi, r in zip(phis, res)]
+    line = {"metric": "NP·steps/s (dipolar+kMC)",
+            "value": n * sets * len(phis) * steps_per_run * args.steps / wall, "unit": "NP·steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 field / f64 barrier", "data": "synthetic",
+            "config": {"workload": "concentration sweep: 3000 NPs, lattice + maximal disorder, "
+                                   "T=0, Ms=1e6, K=1.3e4, 40 mT, 8 axis sets, phi 0.01-30 %",
+                       "A_over_K_vs_dimensionless_concentration": curve}}
     print(json.dumps(line), flush=True)
 
 
