@@ -89,6 +89,18 @@ int mh_ctx_destroy(mh_ctx* ctx);
  * Initial moments are m_i = sign(n_i . x) n_i (sign(0) = +1). */
 int mh_create_assembly(mh_ctx* ctx, int64_t n, const double* pos, const double* axes,
                        int64_t n_axes_sets, const mh_params* params, mh_asm** out);
+
+/* As mh_create_assembly with n_pos_sets position sets (pos: n_pos_sets x n x 3, each
+ * set checked for overlaps): replica r uses position set r mod n_pos_sets, the
+ * paper's second averaging method (Sec. III.1), in which positions as well as axes
+ * change between loops and particle i of every set sits near the same mean position
+ * (for instance the same lattice node). Per-particle outputs therefore refer to that
+ * mean position. The interaction-matrix form holds one matrix per geometry and takes
+ * a single set (MH_EINVAL otherwise); mh_get_local_concentration and mh_debug_field use
+ * set 0. */
+int mh_create_assembly_sets(mh_ctx* ctx, int64_t n, const double* pos, int64_t n_pos_sets,
+                            const double* axes, int64_t n_axes_sets, const mh_params* params,
+                            mh_asm** out);
 int mh_destroy_assembly(mh_asm* a);
 
 /* Runs n_periods x steps_per_period steps for n_replicas independent replicas.

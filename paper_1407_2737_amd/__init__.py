@@ -27,7 +27,7 @@ SYMBOLS = [
     "mh_server_create", "mh_server_submit", "mh_server_poll", "mh_server_destroy",
     "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
     "mh_ctx_autotune", "mh_ctx_load_shapes", "mh_get_dhdip",
-    "mh_get_local_concentration",
+    "mh_get_local_concentration", "mh_create_assembly_sets",
 ]
 
 
@@ -87,6 +87,8 @@ def _lib():
             "mh_ctx_create": ([C.c_int, C.POINTER(vp)], C.c_int),
             "mh_ctx_destroy": ([vp], C.c_int),
             "mh_create_assembly": ([vp, i64, dp, dp, i64, C.POINTER(Params), C.POINTER(vp)], C.c_int),
+            "mh_create_assembly_sets": ([vp, i64, dp, i64, dp, i64, C.POINTER(Params),
+                                         C.POINTER(vp)], C.c_int),
             "mh_destroy_assembly": ([vp], C.c_int),
             "mh_run_loops": ([vp, i64, u64, vp], C.c_int),
             "mh_run_batch": ([C.POINTER(vp), i32, C.POINTER(i64), u64p, vp], C.c_int),
@@ -200,15 +202,23 @@ class Context:
 class Assembly:
     """An assembly of particles (mh_create_assembly) and its last run."""
 
-    def __init__(self, ctx: Context, pos, axes, params: Params, n_axes_sets: int = 1):
+    def __init__(self, ctx: Context, pos, axes, params: Params, n_axes_sets: int = 1,
+                 n_pos_sets: int = 1):
         self.ctx = ctx
         pos = _f64(pos)
-        self.n = pos.shape[0]
+        self.n = pos.shape[0] // n_pos_sets
+        pos = _f64(pos, (n_pos_sets * self.n, 3))
         axes = _f64(axes, (n_axes_sets * self.n, 3))
         self.params = params
         self._h = C.c_void_p()
-        _check(_lib().mh_create_assembly(ctx._h, self.n, _dp(pos), _dp(axes), n_axes_sets,
-                                         C.byref(params), C.byref(self._h)), "mh_create_assembly")
+        if n_pos_sets == 1:
+            _check(_lib().mh_create_assembly(ctx._h, self.n, _dp(pos), _dp(axes), n_axes_sets,
+                                             C.byref(params), C.byref(self._h)),
+                   "mh_create_assembly")
+        else:
+            _check(_lib().mh_create_assembly_sets(ctx._h, self.n, _dp(pos), n_pos_sets, _dp(axes),
+                                                  n_axes_sets, C.byref(params), C.byref(self._h)),
+                   "mh_create_assembly_sets")
         self.R = 0
 
     def close(self):

@@ -143,6 +143,7 @@ struct mh_asm {
   mh_ctx* ctx = nullptr;
   int64_t n = 0;
   int64_t n_axes_sets = 1;
+  int64_t n_pos_sets = 1;  // replica r uses position set r mod n_pos_sets
   mh_params p{};
   // geometry
   DevBuf pos64, pos32, axes;
@@ -253,7 +254,12 @@ int64_t g_bucket(int64_t g) {
   return b;
 }
 int64_t groups_of(const mh_asm* a, int64_t R) {
-  return a->p.precision == MH_FP64 ? R : (R + 3) / 4;
+  if (a->p.precision == MH_FP64) return R;
+  // FP32 groups of up to four replicas that share a position set
+  int64_t g = 0;
+  const int64_t P = std::min<int64_t>(a->n_pos_sets, R);
+  for (int64_t q = 0; q < P; ++q) g += ((R - q + P - 1) / P + 3) / 4;
+  return g;
 }
 
 // Launch shape of the tiled field kernel: an autotuner candidate, else the context's
@@ -346,8 +352,9 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   const mh_params& p = a->p;
   SysDesc s{};
   const int64_t n = a->n;
-  s.pos64 = a->pos64.as<D4>();
-  s.pos32 = a->pos32.as<F4>();
+  const int64_t pset = r % a->n_pos_sets;
+  s.pos64 = a->pos64.as<D4>() + pset * n;
+  s.pos32 = a->pos32.as<F4>() + pset * n;
   s.axes = a->axes.as<D4>() + (r % a->n_axes_sets) * n;
   s.m64 = a->m64.as<D4>() + r * n;
   // FP32 moment copies exist only for the FP32 field form, which is their one reader
@@ -425,19 +432,27 @@ struct Plan {
 
 // The R replicas of one tiled assembly: field blocks take up to 4 replicas at a time in
 // FP32 (they share positions, so the pair geometry is computed once for all of them).
-void add_tiled(Plan& pl, int fp64, int kind, const std::vector<SysDesc>& reps) {
+// Field tiles of one assembly's replicas: FP32 replicas that share a position set
+// (replica r has set r mod P) are grouped four at a time, in replica order within a
+// set, so that a block applies one pair geometry to each group member's moments.
+void add_tiled(Plan& pl, int fp64, int kind, const std::vector<SysDesc>& reps, int64_t P) {
   const int R = (int)reps.size();
   const int TI = tile_width(kind);
   const int Gmax = fp64 ? 1 : 4;
-  for (int g0 = 0; g0 < R; g0 += Gmax) {
-    const int gn = std::min(Gmax, R - g0);
-    const int gi = gidx(fp64, kind, gn);
-    const int sidx = (int)pl.til[gi].size();
-    for (int r = 0; r < gn; ++r) pl.til[gi].push_back(reps[g0 + r]);
-    const int n = reps[0].n;
-    for (int it = 0; it < (n + TI - 1) / TI; ++it)
-      for (int part = 0; part < reps[0].nsplit; ++part)
-        pl.tiles[gi].push_back(int4{sidx, it, gn, part});
+  P = std::max<int64_t>(1, std::min<int64_t>(P, R));
+  for (int64_t q = 0; q < P; ++q) {
+    std::vector<int> mem;
+    for (int r = (int)q; r < R; r += (int)P) mem.push_back(r);
+    for (size_t g0 = 0; g0 < mem.size(); g0 += Gmax) {
+      const int gn = (int)std::min<size_t>(Gmax, mem.size() - g0);
+      const int gi = gidx(fp64, kind, gn);
+      const int sidx = (int)pl.til[gi].size();
+      for (int r = 0; r < gn; ++r) pl.til[gi].push_back(reps[mem[g0 + r]]);
+      const int n = reps[0].n;
+      for (int it = 0; it < (n + TI - 1) / TI; ++it)
+        for (int part = 0; part < reps[0].nsplit; ++part)
+          pl.tiles[gi].push_back(int4{sidx, it, gn, part});
+    }
   }
   for (const SysDesc& s : reps) {
     const int uidx = (int)pl.upd.size();
@@ -527,7 +542,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       pl.kmax = std::max<int64_t>(pl.kmax, s.k_origin + s.total_steps);
       pl.nmax_all = std::max(pl.nmax_all, (int)a->n);
     }
-    if (!reps.empty()) add_tiled(pl, fp64 ? 1 : 0, a->tile_kind, reps);
+    if (!reps.empty()) add_tiled(pl, fp64 ? 1 : 0, a->tile_kind, reps, a->n_pos_sets);
     fin.push_back({a, {first, (int)all.size()}});
     if (a->p.precision == MH_BF16X3_WM) pl.wm.push_back(WMItem{a, first, wm_args(a)});
   }
@@ -1002,14 +1017,19 @@ int mh_ctx_destroy(mh_ctx* c) {
   return MH_OK;
 }
 
-int mh_create_assembly(mh_ctx* c, int64_t n, const double* pos, const double* axes,
-                       int64_t n_axes_sets, const mh_params* params, mh_asm** out) {
+int mh_create_assembly_sets(mh_ctx* c, int64_t n, const double* pos, int64_t n_pos_sets,
+                            const double* axes, int64_t n_axes_sets, const mh_params* params,
+                            mh_asm** out) {
   if (!out) return MH_EINVAL;
   *out = nullptr;
-  if (!c || !pos || !axes || n < 1 || n > (1 << 24) || n_axes_sets < 1) return MH_EINVAL;
+  if (!c || !pos || !axes || n < 1 || n > (1 << 24) || n_axes_sets < 1 || n_pos_sets < 1 ||
+      n_pos_sets > 65536 || n * n_pos_sets > ((int64_t)1 << 28))
+    return MH_EINVAL;
   int e = validate_params(params);
   if (e) return e;
-  for (int64_t i = 0; i < 3 * n; ++i)
+  // one interaction matrix per geometry: the matrix form takes a single position set
+  if (n_pos_sets > 1 && params->precision == MH_BF16X3_WM) return MH_EINVAL;
+  for (int64_t i = 0; i < 3 * n * n_pos_sets; ++i)
     if (!std::isfinite(pos[i])) return MH_EINVAL;
   std::vector<D4> ax((size_t)(n * n_axes_sets));
   for (int64_t i = 0; i < n * n_axes_sets; ++i) {
@@ -1019,27 +1039,30 @@ int mh_create_assembly(mh_ctx* c, int64_t n, const double* pos, const double* ax
     if (!(nn > 0)) return MH_EINVAL;
     ax[i] = D4{x / nn, y / nn, z / nn, 0.0};
   }
-  if ((e = check_overlap(n, pos, params->d))) return e;
+  for (int64_t q = 0; q < n_pos_sets; ++q)
+    if ((e = check_overlap(n, pos + 3 * n * q, params->d))) return e;
   if (set_dev(c)) return MH_EDEVICE;
   mh_asm* a = new (std::nothrow) mh_asm();
   if (!a) return MH_ENOMEM;
   a->ctx = c;
   a->n = n;
   a->n_axes_sets = n_axes_sets;
+  a->n_pos_sets = n_pos_sets;
   a->p = *params;
-  std::vector<D4> p64((size_t)n);
-  std::vector<F4> p32((size_t)n);
-  for (int64_t i = 0; i < n; ++i) {
+  const int64_t np = n * n_pos_sets;
+  std::vector<D4> p64((size_t)np);
+  std::vector<F4> p32((size_t)np);
+  for (int64_t i = 0; i < np; ++i) {
     p64[i] = D4{pos[3 * i] / params->d, pos[3 * i + 1] / params->d, pos[3 * i + 2] / params->d, 0};
     p32[i] = F4{(float)p64[i].x, (float)p64[i].y, (float)p64[i].z, 0.f};
   }
-  if ((e = a->pos64.ensure(sizeof(D4) * n)) || (e = a->pos32.ensure(sizeof(F4) * n)) ||
+  if ((e = a->pos64.ensure(sizeof(D4) * np)) || (e = a->pos32.ensure(sizeof(F4) * np)) ||
       (e = a->axes.ensure(sizeof(D4) * n * n_axes_sets))) {
     mh_destroy_assembly(a);
     return e;
   }
-  if (hipMemcpy(a->pos64.p, p64.data(), sizeof(D4) * n, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(a->pos32.p, p32.data(), sizeof(F4) * n, hipMemcpyHostToDevice) != hipSuccess ||
+  if (hipMemcpy(a->pos64.p, p64.data(), sizeof(D4) * np, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(a->pos32.p, p32.data(), sizeof(F4) * np, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(a->axes.p, ax.data(), sizeof(D4) * n * n_axes_sets, hipMemcpyHostToDevice) !=
           hipSuccess) {
     mh_destroy_assembly(a);
@@ -1047,6 +1070,11 @@ int mh_create_assembly(mh_ctx* c, int64_t n, const double* pos, const double* ax
   }
   *out = a;
   return MH_OK;
+}
+
+int mh_create_assembly(mh_ctx* c, int64_t n, const double* pos, const double* axes,
+                       int64_t n_axes_sets, const mh_params* params, mh_asm** out) {
+  return mh_create_assembly_sets(c, n, pos, 1, axes, n_axes_sets, params, out);
 }
 
 int mh_destroy_assembly(mh_asm* a) {
