@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="config 3: built-in launch-shape rule")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4plain", "c5", "c5wm", "master", "sweep"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4plain", "c5", "c5wm", "master", "sweep", "methods"])
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--max-replicas", type=int, default=64)
     ap.add_argument("--assemblies", type=int, default=256)
@@ -88,6 +88,8 @@ def main():
         return bench_c1(args, mh, W)
     if args.workload == "sweep":
         return bench_sweep(args, mh, W)
+    if args.workload == "methods":
+        return bench_methods(args, mh, W)
     if args.workload in ("c5", "c5wm"):
         return bench_c5(args, mh, W)
     if args.workload != "c2":
@@ -217,6 +219,54 @@ def bench_c1(args, mh, W):
             "roofline": {"bound": "alu", "achieved": flops / out[1024] / 1e12, "peak": 78.6,
                          "unit": "TFLOP/s", "frac": flops / out[1024] / 78.6e12, "traffic": None,
                          "kernel": "k_resident<double> (whole run, pair terms only)"}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_methods(args, mh, W):
+    """The paper's two ways of averaging loops (Sec. III.1, Fig. 3): 5000 particles of
+    20 nm on a maximally disordered cubic lattice at phi = 1 %, K = 1.3e4, Ms = 1e6,
+    300 K, 40 mT, 100 kHz, 50 loops (replicas) of 2 periods (first discarded). Method 1
+    changes only the axes between loops; method 2 changes the axes and the positions
+    (particle i stays near lattice node i). Reports the per-particle area against the
+    normalised distance from the centre after a 200-point moving average, and the rms
+    scatter of the raw per-particle means about it."""
+    import numpy as np
+    n, loops, d, phi = 5000, 50, 20e-9, 0.01
+    radius = 0.5 * d * (n / phi) ** (1.0 / 3.0)
+    mat = W.Material(Ms=1e6, Keff=1.3e4, d=d, T=300.0, mu0Hmax=0.04, n_periods=2, n_discard=1)
+    axes = np.concatenate([W.axes_random_3d(n, 9500 + q) for q in range(loops)])
+    pos_sets = [W.place_lattice_disorder(n, radius, d, 9600 + q) for q in range(loops)]
+    ctx = mh.Context(0)
+    p = mh.params_from_material(mat, mh.FP32_FIELD)
+    m1 = mh.Assembly(ctx, pos_sets[0], axes, p, n_axes_sets=loops)
+    m2 = mh.Assembly(ctx, np.concatenate(pos_sets), axes, p, n_axes_sets=loops, n_pos_sets=loops)
+    # mean positions: the lattice nodes, i.e. the mean over the position sets
+    rnorm = np.linalg.norm(np.mean(pos_sets, axis=0), axis=1) / radius
+    order = np.argsort(rnorm, kind="stable")
+    out, walls = {}, {}
+    for name, a in (("method1_axes", m1), ("method2_axes_and_positions", m2)):
+        t0 = time.perf_counter()
+        a.run(loops, seed=77)
+        a.sync()
+        walls[name] = time.perf_counter() - t0
+        raw = a.sar(per_np=True)["area_per_np"][order]
+        smooth = np.convolve(raw, np.ones(200) / 200, mode="valid")
+        centre = raw[99:99 + smooth.shape[0]]
+        x = rnorm[order][99:99 + smooth.shape[0]]
+        pick = [min(int(np.searchsorted(x, v)), x.shape[0] - 1) for v in (0.2, 0.4, 0.6, 0.8, 0.9, 0.95)]
+        out[name] = {"rms_scatter_about_average_Jm3": float(np.sqrt(np.mean((centre - smooth) ** 2))),
+                     "mean_area_Jm3": float(raw.mean()),
+                     "smoothed_area_at_r": {f"{x[i]:.2f}": float(smooth[i]) for i in pick}}
+    steps = mat.steps_per_period * mat.n_periods
+    line = {"metric": "NP·steps/s (dipolar+kMC)",
+            "value": n * loops * steps / walls["method2_axes_and_positions"], "unit": "NP·steps/s",
+            "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": walls["method2_axes_and_positions"] * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32 field / f64 barrier",
+            "data": "synthetic",
+            "config": {"workload": "averaging methods: 5000 NPs, d=20 nm, phi=1 %, 40 mT, 50 loops "
+                                   "(value: method 2, one geometry per loop)",
+                       "seconds": walls, **out}}
     print(json.dumps(line), flush=True)
 
 
