@@ -155,6 +155,7 @@ def main():
         dh_profile[key] = [float(dh[which == b].mean() * 1e3) for b in range(len(edges) - 1)]
         corr[key] = float(np.corrcoef(dh, a_np)[0, 1])
     phi20 = asm.local_concentration(20)      # Eq. 8
+    field_err = {f"{h * 1e3:g} mT": asm.field_error(r)[0] for r, h in enumerate(amps)}
     analyses = {"dhdip_mT_vs_depth": dh_profile, "corr_dhdip_area": corr,
                 "phi20_vs_depth": [float(phi20[which == b].mean()) for b in range(len(edges) - 1)]}
     line = {
@@ -179,7 +180,8 @@ def main():
                                          "count": [int((which == b).sum())
                                                    for b in range(len(edges) - 1)],
                                          **profile},
-                   "per_particle_analyses": analyses},
+                   "per_particle_analyses": analyses,
+                   "field_rel_error_vs_fp64": field_err},
         "roofline": roofline,
     }
     if not args.no_cpu:
@@ -551,15 +553,8 @@ def bench_c4(args, mh, W):
     # field error of this form on replica 0's final moments, against the FP64 field
     # kernel (which the parity tests hold within 1e-13 of the FP64 oracle): relative
     # Frobenius norm and the largest per-particle error over the rms field
-    m0 = asm.moments(0)
-    b_form = asm.debug_field(m0)
-    a64 = mh.Assembly(ctx, a4.pos, a4.axes[:n], mh.params_from_material(a4.mat, mh.FP64))
-    b_64 = a64.debug_field(m0)
-    a64.close()
-    db = b_form - b_64
-    field_err = {"rel_frobenius": float(np.linalg.norm(db) / np.linalg.norm(b_64)),
-                 "max_over_rms": float(np.linalg.norm(db, axis=1).max()
-                                       / np.sqrt((b_64 ** 2).sum(axis=1).mean()))}
+    rel, mx = asm.field_error(0)
+    field_err = {"rel_frobenius": rel, "max_over_rms": mx}
     line = {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",

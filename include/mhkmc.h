@@ -160,6 +160,15 @@ int mh_get_replica_areas(mh_asm* a, double* area);
  * any run. */
 int mh_get_area_per_np(mh_asm* a, int64_t replica, double* area_per_np);
 
+/* Error of the assembly's field form on one replica's current moments: the Eq. 1 field
+ * computed by the assembly's precision (FP32 sums or the BF16x3 matrix product) against
+ * the FP64 kernel, as the relative Frobenius norm over all particles and components and
+ * as the largest per-particle error over the rms field. Computed on temporary copies of
+ * the geometry; the assembly's run and results are left as they are. 0 for FP64, without
+ * interactions or for one particle. Synchronous; MH_EINVAL for a replica outside the
+ * last run, MH_ENOTREADY before any run. */
+int mh_get_field_error(mh_asm* a, int64_t replica, double* rel_frobenius, double* max_over_rms);
+
 /* Eq. 6 per particle of one replica (n values, tesla): the x component of the dipolar
  * field acting in the +mu0 Hmax step (k = 0 mod S, from that step's start-of-step
  * moments) minus that in the -mu0 Hmax step (k = S/2 mod S), averaged over the kept

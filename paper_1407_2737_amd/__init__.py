@@ -27,7 +27,7 @@ SYMBOLS = [
     "mh_server_create", "mh_server_submit", "mh_server_poll", "mh_server_destroy",
     "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
     "mh_ctx_autotune", "mh_ctx_load_shapes", "mh_get_dhdip",
-    "mh_get_local_concentration", "mh_create_assembly_sets",
+    "mh_get_local_concentration", "mh_create_assembly_sets", "mh_get_field_error",
 ]
 
 
@@ -99,6 +99,7 @@ def _lib():
             "mh_get_moments": ([vp, i64, dp], C.c_int),
             "mh_get_area_per_np": ([vp, i64, dp], C.c_int),
             "mh_get_dhdip": ([vp, i64, dp], C.c_int),
+            "mh_get_field_error": ([vp, i64, dp, dp], C.c_int),
             "mh_get_local_concentration": ([vp, i32, dp], C.c_int),
             "mh_run_mean_loop": ([vp, i64, vp], C.c_int),
             "mh_ctx_autotune": ([vp, i32, C.POINTER(i64), i32, C.POINTER(i64), i32, C.c_char_p],
@@ -284,6 +285,13 @@ class Assembly:
         _check(_lib().mh_get_local_concentration(self._h, N, _dp(out)),
                "mh_get_local_concentration")
         return out
+
+    def field_error(self, replica: int = 0):
+        """(relative Frobenius, max over rms) of this form's field against FP64."""
+        rel, mx = C.c_double(), C.c_double()
+        _check(_lib().mh_get_field_error(self._h, replica, C.byref(rel), C.byref(mx)),
+               "mh_get_field_error")
+        return rel.value, mx.value
 
     def dhdip(self, replica: int = 0) -> np.ndarray:
         """Eq. 6 per particle of one replica, tesla (mean over kept periods)."""

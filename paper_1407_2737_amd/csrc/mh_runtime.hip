@@ -1220,6 +1220,58 @@ int mh_get_local_concentration(mh_asm* a, int32_t N, double* phi) {
   return MH_OK;
 }
 
+int mh_get_field_error(mh_asm* a, int64_t replica, double* rel_frobenius, double* max_over_rms) {
+  if (!a || !rel_frobenius || !max_over_rms) return MH_EINVAL;
+  int e = mh_sync(a);
+  if (e) return e;
+  if (replica < 0 || replica >= a->R) return MH_EINVAL;
+  const int64_t n = a->n;
+  if (n < 2 || !a->p.interactions) {  // no dipolar field: nothing to approximate
+    *rel_frobenius = *max_over_rms = 0.0;
+    return MH_OK;
+  }
+  std::vector<double> m((size_t)(3 * n)), pos((size_t)(3 * n)), ax((size_t)(3 * n));
+  if ((e = mh_get_moments(a, replica, m.data()))) return e;
+  // the replica's geometry, back in metres, for two temporary assemblies
+  std::vector<D4> p4((size_t)n);
+  const int64_t pset = replica % a->n_pos_sets;
+  if (hipMemcpy(p4.data(), a->pos64.as<D4>() + pset * n, sizeof(D4) * n, hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return MH_EDEVICE;
+  for (int64_t i = 0; i < n; ++i) {
+    pos[3 * i] = p4[i].x * a->p.d;
+    pos[3 * i + 1] = p4[i].y * a->p.d;
+    pos[3 * i + 2] = p4[i].z * a->p.d;
+    ax[3 * i] = 1.0;
+    ax[3 * i + 1] = ax[3 * i + 2] = 0.0;
+  }
+  std::vector<double> bf((size_t)(3 * n)), b64((size_t)(3 * n));
+  mh_params p = a->p;
+  for (int pass = 0; pass < 2; ++pass) {
+    p.precision = pass == 0 ? a->p.precision : MH_FP64;
+    mh_asm* t = nullptr;
+    if ((e = mh_create_assembly(a->ctx, n, pos.data(), ax.data(), 1, &p, &t))) return e;
+    e = mh_debug_field(t, m.data(), pass == 0 ? bf.data() : b64.data());
+    mh_destroy_assembly(t);
+    if (e) return e;
+  }
+  double num = 0.0, den = 0.0, worst = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double di = 0.0, bi = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double dd = bf[3 * i + c] - b64[3 * i + c];
+      di += dd * dd;
+      bi += b64[3 * i + c] * b64[3 * i + c];
+    }
+    num += di;
+    den += bi;
+    worst = std::max(worst, di);
+  }
+  *rel_frobenius = den > 0.0 ? std::sqrt(num / den) : 0.0;
+  *max_over_rms = den > 0.0 ? std::sqrt(worst / (den / (double)n)) : 0.0;
+  return MH_OK;
+}
+
 int mh_get_dhdip(mh_asm* a, int64_t replica, double* dhdip_T) {
   if (!a || !dhdip_T) return MH_EINVAL;
   int e = mh_sync(a);

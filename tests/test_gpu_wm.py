@@ -107,3 +107,33 @@ def test_fp32_sar_matches_fp64_path(ctx, lib):
     tol = max(0.01 * abs(s64["area"]), 2 * np.hypot(s64["area_se"], s32["area_se"]))
     print(f"area FP64 {s64['area']:.5g} +- {s64['area_se']:.2g}, FP32 {s32['area']:.5g} +- {s32['area_se']:.2g}")
     assert abs(s64["area"] - s32["area"]) < tol
+
+
+def test_field_error_per_result(ctx, lib):
+    """mh_get_field_error states the field error of a finished run (matrix form and FP32)
+    against the FP64 kernel and against the oracle's Eq. 1 on the same moments, and
+    leaves the run's results untouched."""
+    from oracle import kmc
+    n = 800
+    pos = W.place_random(n, 110e-9, 12e-9, 95)
+    axes = W.axes_random_3d(n, 96)
+    kw = _kw(steps_per_period=100, n_periods=2, n_discard=1)
+    for prec, lim in ((lib.BF16X3_WM, 1e-3), (lib.FP32_FIELD, 1e-5), (lib.FP64, 0.0)):
+        a = lib.Assembly(ctx, pos, axes, lib.Params.make(prec, **kw))
+        a.run(4, seed=3)
+        a.sync()
+        areas, m = a.replica_areas().copy(), a.moments(2).copy()
+        rel, mx = a.field_error(2)
+        # the run's results are untouched
+        assert np.array_equal(a.replica_areas(), areas) and np.array_equal(a.moments(2), m)
+        print(f"precision {prec}: field error {rel:.3e} (max/rms {mx:.3e})")
+        assert rel <= lim and mx < 20 * max(lim, 1e-16)
+        if prec == lib.FP64:
+            assert rel == 0.0
+        else:
+            # the same comparison against the oracle's Eq. 1 agrees with the stated error
+            got = a.debug_field(m)
+            ref = kmc.dipolar_field(pos, m, kmc.derived(kmc.Params(d=12e-9))["C"])
+            e_or = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            assert abs(e_or - rel) < 0.05 * rel + 1e-12
+        a.close()
