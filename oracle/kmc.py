@@ -54,6 +54,7 @@ class Params:
     dt_override: float = 0.0
     prob_form: int = 0
     interactions: int = 1
+    extrema_mode: int = 0    # 0: exact stationary points; 1: the paper's 200-point scan
 
     @classmethod
     def from_dict(cls, d):
@@ -176,7 +177,8 @@ def step(pos, axes, m, k, p: Params, seed: int, stream: int, B_override=None):
         return m_new, StepInfo(B, z, z, z, z, z, z, z, z, np.zeros(n, bool), z, z,
                                np.zeros(n, bool), None, Bdip)
     u2, hx, hy, theta0 = working_plane(B, axes, m, dv["BK"])
-    theta, is_min, count = sw.stationary_points(hx, hy)
+    scan = sw.stationary_points_scan200 if p.extrema_mode == 1 else sw.stationary_points
+    theta, is_min, count = scan(hx, hy)
     th_c, e_c, th_o, e_o, e3, two = sw.classify(theta0, theta, is_min, count, hx, hy)
     th_new = th_c.copy()
     P = np.zeros(n)

@@ -17,6 +17,8 @@ are found than the Stoner-Wohlfarth astroid demands (two minima exactly when
 (hx^2 + hy^2 - 1)^3 + 27 hx^2 hy^2 < 0), so pairs of extrema closer than the grid
 spacing near the switching field are not lost.
 """
+import math
+
 import numpy as np
 
 SCAN = 256
@@ -99,6 +101,65 @@ def stationary_points(hx, hy):
     theta = np.take_along_axis(theta, order, axis=1)
     is_min = np.take_along_axis(is_min, order, axis=1)
     return theta, is_min, count
+
+
+SCAN_PAPER = 200
+
+
+def _wrap(x):
+    """Angle into (-pi, pi] through the IEEE remainder by 2 pi."""
+    r = np.array([math.remainder(float(v), 2.0 * np.pi) for v in np.ravel(x)])
+    return np.where(r == -np.pi, np.pi, r)
+
+
+def stationary_points_scan200(hx, hy):
+    """The paper's step iv taken literally (paper-literal mode): g on the 200 angles
+    theta_j = 2 pi j / 200 of [0, 2 pi), each sign change between neighbours (cyclically)
+    marks an extremum, refined by Newton's method on g from the middle of its interval
+    (at most 50 steps, stopping once a step is below 1e-13); a minimum where g goes from
+    negative to positive. Pairs of extrema closer than the grid spacing near the
+    switching field are missed, as with the paper's scan. Same output layout as
+    stationary_points (count in {2, 4})."""
+    hx = np.atleast_1d(np.asarray(hx, dtype=np.float64))
+    hy = np.atleast_1d(np.asarray(hy, dtype=np.float64))
+    n = hx.shape[0]
+    j = np.arange(SCAN_PAPER + 1)
+    t = 2.0 * np.pi * j / 200.0
+    G = g(t[None, :SCAN_PAPER], hx[:, None], hy[:, None])
+    G = np.concatenate([G, G[:, :1]], axis=1)           # the value at 2 pi is the one at 0
+    neg = G < 0.0
+    change = neg[:, :-1] != neg[:, 1:]
+    count = np.minimum(change.sum(axis=1), 4).astype(np.int64)
+    # the first four sign changes of each row, in grid order
+    rank = np.cumsum(change, axis=1) - 1
+    slot = np.where(change & (rank < 4), rank, 4)
+    k_of = np.full((n, 5), -1, dtype=np.int64)
+    rows = np.broadcast_to(np.arange(n)[:, None], slot.shape)
+    k_of[rows[slot < 4], slot[slot < 4]] = np.broadcast_to(j[None, :SCAN_PAPER],
+                                                           slot.shape)[slot < 4]
+    k_of = k_of[:, :4]
+    valid = k_of >= 0
+    kk = np.where(valid, k_of, 0)
+    # Newton on g from each interval's middle; an element stops after the first step
+    # below 1e-13 (that step is still taken), or after 50 steps
+    x = 0.5 * (t[kk] + t[kk + 1])
+    live = valid.copy()
+    HX, HY = hx[:, None], hy[:, None]
+    for _ in range(50):
+        if not live.any():
+            break
+        sn, cs = np.sin(x), np.cos(x)
+        f = sn * cs + HX * sn - HY * cs
+        d = (cs * cs - sn * sn) + HX * cs + HY * sn
+        dx = np.where(live, f / np.where(live, d, 1.0), 0.0)
+        x = np.where(live, x - dx, x)
+        live &= ~(np.abs(dx) < 1e-13)
+    theta = np.where(valid, _wrap(x).reshape(n, 4), np.nan)
+    is_min = valid & np.take_along_axis(neg, kk, axis=1)
+    key = np.where(np.isnan(theta), np.inf, theta)
+    order = np.argsort(key, axis=1, kind="stable")
+    return (np.take_along_axis(theta, order, axis=1), np.take_along_axis(is_min, order, axis=1),
+            count)
 
 
 def _refine_row(hx, hy, want):

@@ -102,3 +102,45 @@ def test_fall_rules():
     for x in maxs:
         tc, *_ = sw.classify(np.array([x]), th, mn, cnt, hx, hy)
         assert tc[0] == mins[np.argmin(e)]
+
+
+def test_scan200_matches_exact_away_from_switching():
+    """The paper's literal 200-point scan + Newton finds the same stationary points as the
+    exact search wherever the astroid margin is not small."""
+    rng = np.random.default_rng(21)
+    h = rng.uniform(0, 2.0, 3000)
+    phi = rng.uniform(0, np.pi, 3000)
+    hx, hy = h * np.cos(phi), h * np.sin(phi)
+    a = hx * hx + hy * hy - 1.0
+    margin = np.abs(a ** 3 + 27 * hx * hx * hy * hy)
+    keep = margin > 0.05
+    hx, hy = hx[keep], hy[keep]
+    t1, m1, c1 = sw.stationary_points(hx, hy)
+    t2, m2, c2 = sw.stationary_points_scan200(hx, hy)
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(m1, m2)
+    assert np.nanmax(np.abs(t1 - t2)) < 1e-12
+
+
+def test_scan200_misses_close_pair_near_switching_field():
+    """With the field 10 deg off the easy axis at 0.9999 of the astroid's switching field,
+    the saddle and the metastable minimum (2.6223 and 2.6387 rad) both fall inside grid
+    cell 83 of the 200-point scan (width 2 pi / 200): the literal scan has no sign change
+    there and keeps only the stable pair.  At 0.999 of it they are 0.05 rad apart and
+    both are found, identical to the exact search."""
+    phi = np.deg2rad(10.0)
+    h_sw = (np.cos(phi) ** (2 / 3) + np.sin(phi) ** (2 / 3)) ** -1.5
+    for f, want in ((0.9999, 2), (0.999, 4)):
+        hx, hy = np.array([f * h_sw * np.cos(phi)]), np.array([f * h_sw * np.sin(phi)])
+        t1, m1, c_exact = sw.stationary_points(hx, hy)
+        t2, m2, c_scan = sw.stationary_points_scan200(hx, hy)
+        assert c_exact[0] == 4
+        assert c_scan[0] == want
+        # the stable minimum and the maximum it keeps are the exact ones either way
+        assert np.allclose(t2[0, :2], t1[0, :2], atol=1e-13, rtol=0)
+        assert np.array_equal(m2[0, :2], m1[0, :2])
+    # the lost pair leaves a single well: every start falls to the one minimum
+    hx = np.array([0.9999 * h_sw * np.cos(phi)])
+    hy = np.array([0.9999 * h_sw * np.sin(phi)])
+    t2, m2, c2 = sw.stationary_points_scan200(hx, hy)
+    assert m2[0, :2].sum() == 1
