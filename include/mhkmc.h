@@ -53,6 +53,20 @@ extern "C" {
 #define MH_P_TWO_STATE 0   /* Eq. 5: nu_c/(nu_c+nu_o) (1 - exp(-(nu_c+nu_o) dt)) */
 #define MH_P_SINGLE_RATE 1 /* 1 - exp(-nu_c dt): the one-rate limit of Eq. 5 */
 
+/* search for the energy extrema of one particle in its working plane (Sec. II.1, step iv) */
+#define MH_EXTREMA_EXACT 0   /* every stationary point of Eq. 2, found by sign-change
+                                brackets and Newton polish in direction form; the two
+                                minima are present exactly when the field lies inside
+                                the Stoner-Wohlfarth astroid */
+#define MH_EXTREMA_SCAN200 1 /* the paper's search taken literally: dE/dtheta sampled on
+                                200 angles 2 pi j/200, each sign change refined by Newton's
+                                method from its interval's midpoint (at most 50 steps, until
+                                a step is below 1e-13). Within about 1e-4 of the switching
+                                field a saddle and the minimum beside it can share one grid
+                                interval and are then missed: the particle switches that
+                                much early. FP64 sin/cos per grid point, so several times
+                                slower per particle step than MH_EXTREMA_EXACT */
+
 typedef struct mh_ctx mh_ctx;
 typedef struct mh_asm mh_asm;
 
@@ -73,7 +87,8 @@ typedef struct {
   int32_t prob_form;        /* MH_P_TWO_STATE or MH_P_SINGLE_RATE */
   int32_t precision;        /* MH_FP64, MH_FP32_FIELD or MH_BF16X3_WM */
   int32_t interactions;     /* 1: Eq. 1 on; 0: off (the paper's validation mode, Sec. II.3) */
-  int32_t reserved[2];      /* must be 0 */
+  int32_t extrema_mode;     /* MH_EXTREMA_EXACT or MH_EXTREMA_SCAN200 */
+  int32_t reserved;         /* must be 0 */
 } mh_params;
 
 /* Context bound to one HIP device; owns a default stream. */
@@ -132,8 +147,8 @@ int mh_run_batch(mh_asm* const* asms, int32_t count, const int64_t* n_replicas,
  * numbers are drawn. Results are read with mh_get_loop, mh_get_sar,
  * mh_get_replica_areas and mh_get_area_per_np as after mh_run_loops; mh_get_moments
  * gives the expected moments. Asynchronous like mh_run_loops (hip_stream NULL = the
- * library's stream). MH_EINVAL unless params.interactions == 0 and Keff > 0, or for
- * n_replicas outside [1, 65535]. */
+ * library's stream). MH_EINVAL unless params.interactions == 0, Keff > 0 and
+ * extrema_mode == MH_EXTREMA_EXACT, or for n_replicas outside [1, 65535]. */
 int mh_run_mean_loop(mh_asm* a, int64_t n_replicas, void* hip_stream);
 
 /* Waits for the assembly's last run. */
@@ -203,6 +218,13 @@ int mh_debug_philox(mh_ctx* ctx, uint64_t seed, uint64_t stream, int64_t n_block
  * energies in units of K V (Eq. 2 divided by K V), angles in (-pi, pi]. */
 int mh_debug_sw(mh_ctx* ctx, int64_t n, const double* hx, const double* hy,
                 const double* theta0, double* out);
+
+/* As mh_debug_sw with the extremum search of step iv chosen: MH_EXTREMA_EXACT (the same
+ * as mh_debug_sw) or MH_EXTREMA_SCAN200 (Sec. II.1 step iv taken literally; with fewer
+ * than four points found, theta_o = theta_c, e_o = e_c, e3 = NaN, two = 0). MH_EINVAL
+ * for another mode or the input errors of mh_debug_sw. */
+int mh_debug_sw_mode(mh_ctx* ctx, int32_t extrema_mode, int64_t n, const double* hx,
+                     const double* hy, const double* theta0, double* out);
 
 /* Dipolar field of Eq. 1 (T) for moments m (n x 3) of an assembly, as summed by the
  * precision the assembly was created with. B_out: n x 3. */

@@ -15,7 +15,8 @@ idea but makes it exact: a dense scan, bisection of every sign change down to
 adjacent doubles, and a rescan at finer resolution whenever fewer stationary points
 are found than the Stoner-Wohlfarth astroid demands (two minima exactly when
 (hx^2 + hy^2 - 1)^3 + 27 hx^2 hy^2 < 0), so pairs of extrema closer than the grid
-spacing near the switching field are not lost.
+spacing near the switching field are not lost. stationary_points_scan200 is the
+paper's search taken literally (a selectable mode), with the loss of such pairs.
 """
 import math
 

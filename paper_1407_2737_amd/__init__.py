@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmhkmc.so")
 
 FP64, FP32_FIELD, BF16X3_WM = 0, 1, 2
 P_TWO_STATE, P_SINGLE_RATE = 0, 1
+EXTREMA_EXACT, EXTREMA_SCAN200 = 0, 1
 ENOTREADY = -5
 
 SYMBOLS = [
@@ -28,6 +29,7 @@ SYMBOLS = [
     "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
     "mh_ctx_autotune", "mh_ctx_load_shapes", "mh_get_dhdip",
     "mh_get_local_concentration", "mh_create_assembly_sets", "mh_get_field_error",
+    "mh_debug_sw_mode",
 ]
 
 
@@ -43,14 +45,15 @@ class Params(C.Structure):
                 ("mu0Hmax", C.c_double), ("dt_override", C.c_double),
                 ("steps_per_period", C.c_int32), ("n_periods", C.c_int32),
                 ("n_discard", C.c_int32), ("prob_form", C.c_int32), ("precision", C.c_int32),
-                ("interactions", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("interactions", C.c_int32), ("extrema_mode", C.c_int32),
+                ("reserved", C.c_int32)]
 
     @classmethod
     def make(cls, precision: int = FP64, **kw) -> "Params":
         p = cls()
         defaults = dict(Ms=4.0e5, Keff=1.3e4, d=12e-9, T=300.0, tau0=1e-10, rho=5200.0, f=1e5,
                         mu0Hmax=0.02, dt_override=0.0, steps_per_period=2000, n_periods=3,
-                        n_discard=2, prob_form=0, interactions=1)
+                        n_discard=2, prob_form=0, interactions=1, extrema_mode=0)
         defaults.update({k: v for k, v in kw.items() if k in defaults})
         for k, v in defaults.items():
             setattr(p, k, v)
@@ -108,6 +111,7 @@ def _lib():
             "mh_debug_steps": ([vp, i64, u64, i64, i64, dp, dp], C.c_int),
             "mh_debug_philox": ([vp, u64, u64, i64, u64p, u64p], C.c_int),
             "mh_debug_sw": ([vp, i64, dp, dp, dp, dp], C.c_int),
+            "mh_debug_sw_mode": ([vp, i32, i64, dp, dp, dp, dp], C.c_int),
             "mh_debug_field": ([vp, dp, dp], C.c_int),
             "mh_strerror": ([C.c_int], C.c_char_p),
             "mh_ctx_set_timing": ([vp, C.c_int], C.c_int),
@@ -192,11 +196,15 @@ class Context:
                                       out.ctypes.data_as(p)), "mh_debug_philox")
         return out
 
-    def debug_sw(self, hx, hy, theta0) -> np.ndarray:
+    def debug_sw(self, hx, hy, theta0, extrema_mode: int = EXTREMA_EXACT) -> np.ndarray:
         hx, hy, th = _f64(hx).ravel(), _f64(hy).ravel(), _f64(theta0).ravel()
         out = np.empty((hx.shape[0], 6))
-        _check(_lib().mh_debug_sw(self._h, hx.shape[0], _dp(hx), _dp(hy), _dp(th), _dp(out)),
-               "mh_debug_sw")
+        if extrema_mode == EXTREMA_EXACT:
+            _check(_lib().mh_debug_sw(self._h, hx.shape[0], _dp(hx), _dp(hy), _dp(th), _dp(out)),
+                   "mh_debug_sw")
+        else:
+            _check(_lib().mh_debug_sw_mode(self._h, extrema_mode, hx.shape[0], _dp(hx), _dp(hy),
+                                           _dp(th), _dp(out)), "mh_debug_sw_mode")
         return out
 
 

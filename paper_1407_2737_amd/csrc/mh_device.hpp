@@ -369,6 +369,157 @@ __device__ SWState sw_fall(double hx, double hy, Dir d0) {
   return r;
 }
 
+// Steps iv-v with step iv as the paper states it (200-point scan, Newton refinement)
+// instead of the exact search of sw_fall. g = e'/2 is sampled at the 200 angles
+// 2 pi j / 200 of [0, 2 pi), the value at 2 pi being the one at 0. Each sign change
+// between neighbours (cyclically, the first four in grid order) marks one extremum,
+// refined by Newton's method on g from the middle of its interval: at most 50 steps,
+// the first one below 1e-13 being the last, the result wrapped into (-pi, pi] by the
+// IEEE remainder. Products and sums are not fused here, so that the signs of g on the
+// grid, which fix the number of extrema, are rounded as in plain FP64 arithmetic. A point is a minimum where g turns from negative to positive. Near
+// the switching field a saddle and the minimum beside it can share one grid interval
+// and are then not seen: the particle keeps only its stable well.
+// Step v on the sorted points (ascending angle, stable): with four points the moment
+// at theta0 = atan2(d0) falls into the minimum at the end of its arc, one that sits
+// exactly on a maximum into the lower minimum, then the nearer; with fewer points into
+// the first minimum. Kept out of line: it is selected per system at run time and is
+// far heavier than sw_fall.
+namespace scan200 {
+
+struct Pt {
+  double t;   // angle, or NaN
+  bool mn;    // minimum
+};
+
+__device__ __forceinline__ double key(const Pt& p) { return isnan(p.t) ? INFINITY : p.t; }
+
+__device__ __forceinline__ void order(Pt& a, Pt& b) {
+  if (key(a) > key(b)) {
+    const Pt t = a;
+    a = b;
+    b = t;
+  }
+}
+
+__device__ __forceinline__ Pt at(int k, const Pt& p0, const Pt& p1, const Pt& p2,
+                                 const Pt& p3) {
+  return k == 0 ? p0 : (k == 1 ? p1 : (k == 2 ? p2 : p3));
+}
+
+__device__ __forceinline__ double refine(double x, double hx, double hy) {
+#pragma clang fp contract(off)
+  for (int it = 0; it < 50; ++it) {
+    double s, c;
+    sincos(x, &s, &c);
+    const double f = s * c + hx * s - hy * c;
+    const double d = (c * c - s * s) + hx * c + hy * s;
+    const double dx = f / d;
+    x -= dx;
+    if (fabs(dx) < 1e-13) break;
+  }
+  const double r = remainder(x, 2.0 * kPi);
+  return r == -kPi ? kPi : r;
+}
+
+__device__ __forceinline__ double energy_at(double t, double hx, double hy) {
+#pragma clang fp contract(off)
+  double s, c;
+  sincos(isnan(t) ? 0.0 : t, &s, &c);
+  return s * s - 2.0 * (hx * c + hy * s);
+}
+
+}  // namespace scan200
+
+__device__ __noinline__ SWState sw_fall_scan200(double hx, double hy, Dir d0) {
+#pragma clang fp contract(off)
+  using namespace scan200;
+  Pt p0{NAN, false}, p1{NAN, false}, p2{NAN, false}, p3{NAN, false};
+  int cnt = 0;
+  double s, c;
+  sincos(0.0, &s, &c);
+  const bool neg0 = s * c + hx * s - hy * c < 0.0;
+  bool neg_prev = neg0;
+  double t_prev = 0.0;
+  for (int j = 1; j <= 200; ++j) {
+    const double t = 2.0 * kPi * (double)j / 200.0;
+    bool neg = neg0;
+    if (j < 200) {
+      sincos(t, &s, &c);
+      neg = s * c + hx * s - hy * c < 0.0;
+    }
+    if (neg != neg_prev && cnt < 4) {
+      const Pt q{refine(0.5 * (t_prev + t), hx, hy), neg_prev};
+      if (cnt == 0) p0 = q;
+      if (cnt == 1) p1 = q;
+      if (cnt == 2) p2 = q;
+      if (cnt == 3) p3 = q;
+      ++cnt;
+    }
+    neg_prev = neg;
+    t_prev = t;
+  }
+  // stable sort by angle (adjacent exchanges on strict order), NaN last
+  order(p0, p1);
+  order(p1, p2);
+  order(p2, p3);
+  order(p0, p1);
+  order(p1, p2);
+  order(p0, p1);
+  const double e0 = energy_at(p0.t, hx, hy), e1 = energy_at(p1.t, hx, hy);
+  const double e2 = energy_at(p2.t, hx, hy), e3 = energy_at(p3.t, hx, hy);
+  auto energy_of = [&](int k) { return k == 0 ? e0 : (k == 1 ? e1 : (k == 2 ? e2 : e3)); };
+  const bool two = cnt == 4;
+  int ic, io;
+  if (!two) {
+    const bool v0 = p0.mn && !isnan(p0.t), v1 = p1.mn && !isnan(p1.t);
+    const bool v2 = p2.mn && !isnan(p2.t), v3 = p3.mn && !isnan(p3.t);
+    ic = v0 ? 0 : (v1 ? 1 : (v2 ? 2 : (v3 ? 3 : 0)));
+    io = ic;
+  } else {
+    const double t0 = atan2(d0.s, d0.c);
+    const int j = (p0.t < t0) + (p1.t < t0) + (p2.t < t0) + (p3.t < t0);
+    const int left = (j + 3) & 3, right = j & 3;
+    ic = at(left, p0, p1, p2, p3).mn ? left : right;
+    int hit = -1;
+    if (p3.t == t0) hit = 3;
+    if (p2.t == t0) hit = 2;
+    if (p1.t == t0) hit = 1;
+    if (p0.t == t0) hit = 0;
+    // the two minima in slot order
+    const int ma = p0.mn ? 0 : (p1.mn ? 1 : (p2.mn ? 2 : 3));
+    const int mb = p3.mn ? 3 : (p2.mn ? 2 : (p1.mn ? 1 : 0));
+    if (hit >= 0) {
+      if (at(hit, p0, p1, p2, p3).mn) {
+        ic = hit;
+      } else if (energy_of(ma) != energy_of(mb)) {
+        ic = energy_of(ma) < energy_of(mb) ? ma : mb;
+      } else {
+        const double da = fabs(wrap_pi(t0 - at(ma, p0, p1, p2, p3).t));
+        const double db = fabs(wrap_pi(t0 - at(mb, p0, p1, p2, p3).t));
+        ic = da <= db ? ma : mb;
+      }
+    }
+    io = ic == ma ? mb : ma;
+  }
+  SWState r;
+  r.two = two;
+  const double tc = at(ic, p0, p1, p2, p3).t, to = at(io, p0, p1, p2, p3).t;
+  sincos(isnan(tc) ? 0.0 : tc, &r.s_c, &r.c_c);
+  sincos(isnan(to) ? 0.0 : to, &r.s_o, &r.c_o);
+  r.e_c = energy_of(ic);
+  r.e_o = energy_of(io);
+  r.e3 = NAN;
+  if (two) {
+    double lo = INFINITY;
+    if (!p0.mn) lo = fmin(lo, e0);
+    if (!p1.mn) lo = fmin(lo, e1);
+    if (!p2.mn) lo = fmin(lo, e2);
+    if (!p3.mn) lo = fmin(lo, e3);
+    r.e3 = lo;
+  }
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Per-particle update (steps iii-vii)
 // ---------------------------------------------------------------------------
@@ -378,6 +529,7 @@ struct NPParams {
   double beta;      // K V / (k_B T)
   double nu0dt;     // dt / tau0
   int prob_form;    // 0: Eq. 5, 1: single rate
+  int scan200;      // step iv as the 200-point scan (sw_fall_scan200), else the exact search
   int thermal;      // T > 0
   int aniso;        // K > 0
 };
@@ -466,6 +618,9 @@ __device__ __forceinline__ void transition_pair(const NPParams& p, double a_c, d
   P_oc = (xo * r) * q;
 }
 
+// kScan: the kernel also serves systems whose step iv is the 200-point scan (p.scan200);
+// without it that search is not compiled in, so the exact path keeps its registers.
+template <bool kScan = false>
 __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz, double nx,
                               double ny, double nz, double mx, double my, double mz,
                               uint64_t seed, uint64_t stream, int64_t i, int64_t k) {
@@ -489,7 +644,8 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
   // step iii
   const Plane w = working_plane(p, Bx, By, Bz, nx, ny, nz, mx, my, mz);
   // steps iv-v
-  const SWState sw = sw_fall(w.hx, w.hy, w.d0);
+  const SWState sw = (kScan && p.scan200) ? sw_fall_scan200(w.hx, w.hy, w.d0)
+                                          : sw_fall(w.hx, w.hy, w.d0);
   double s = sw.s_c, c = sw.c_c;
   out.two = sw.two;
   // steps vi-vii

@@ -109,7 +109,7 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
 // Resident form: one workgroup of 256 threads per system, steps [k0, k1).
 // Dynamic LDS: pos[nmax] then mom[2][nmax] (field precision T).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool kScan>
 __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ systems,
                                                   int64_t k0, int64_t k1, int nmax) {
   using P4 = typename V4<T>::type;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ sy
         bz += __shfl_xor(bz, off, 64);
       }
       if (i < n && sub == 0) {
-        const double mx = np_epilogue(s, i, k, cur, (double)bx, (double)by, (double)bz);
+        const double mx = np_epilogue<kScan>(s, i, k, cur, (double)bx, (double)by, (double)bz);
         mxsum += mx;
         if (s.field_only) continue;
         const D4 m = s.m64[(int64_t)(cur ^ 1) * s.stride + i];
@@ -351,6 +351,7 @@ __global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ s
   }
 }
 
+template <bool kScan>
 __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ systems,
                                                 const int2* __restrict__ blocks,
                                                 const int64_t* __restrict__ kbase, int64_t koff) {
@@ -370,7 +371,7 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
       fy += f.y;
       fz += f.z;
     }
-    mx = np_epilogue(s, i, k, cur, fx, fy, fz);
+    mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz);
   }
   if (k >= s.kept0 && !s.field_only) {
     const double tot = block_sum_256(mx, red);
@@ -578,12 +579,13 @@ __global__ void k_philox_raw(uint64_t seed, uint64_t stream, const uint64_t* __r
 }
 
 __global__ void k_sw(const double* __restrict__ hx, const double* __restrict__ hy,
-                     const double* __restrict__ th0, double* __restrict__ out, int64_t n) {
+                     const double* __restrict__ th0, double* __restrict__ out, int64_t n,
+                     int scan200) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   Dir d;
   sincos(th0[i], &d.s, &d.c);
-  const SWState r = sw_fall(hx[i], hy[i], d);
+  const SWState r = scan200 ? sw_fall_scan200(hx[i], hy[i], d) : sw_fall(hx[i], hy[i], d);
   double* o = out + 6 * i;
   o[0] = atan2(r.s_c, r.c_c);
   o[1] = r.e_c;
@@ -596,15 +598,25 @@ __global__ void k_sw(const double* __restrict__ hx, const double* __restrict__ h
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_resident(bool fp64, const SysDesc* d_sys, int nsys, int64_t k0, int64_t k1,
-                           int nmax, hipStream_t st) {
+hipError_t launch_resident(bool fp64, bool scan, const SysDesc* d_sys, int nsys, int64_t k0,
+                           int64_t k1, int nmax, hipStream_t st) {
   if (nsys == 0) return hipSuccess;
   if (fp64) {
     const size_t lds = (size_t)nmax * 3 * sizeof(D4);
-    hipLaunchKernelGGL(k_resident<double>, dim3(nsys), dim3(256), lds, st, d_sys, k0, k1, nmax);
+    if (scan)
+      hipLaunchKernelGGL((k_resident<double, true>), dim3(nsys), dim3(256), lds, st, d_sys, k0, k1,
+                         nmax);
+    else
+      hipLaunchKernelGGL((k_resident<double, false>), dim3(nsys), dim3(256), lds, st, d_sys, k0,
+                         k1, nmax);
   } else {
     const size_t lds = (size_t)nmax * 3 * sizeof(F4);
-    hipLaunchKernelGGL(k_resident<float>, dim3(nsys), dim3(256), lds, st, d_sys, k0, k1, nmax);
+    if (scan)
+      hipLaunchKernelGGL((k_resident<float, true>), dim3(nsys), dim3(256), lds, st, d_sys, k0, k1,
+                         nmax);
+    else
+      hipLaunchKernelGGL((k_resident<float, false>), dim3(nsys), dim3(256), lds, st, d_sys, k0, k1,
+                         nmax);
   }
   return hipGetLastError();
 }
@@ -614,11 +626,14 @@ size_t resident_lds_bytes(bool fp64, int nmax) {
 }
 
 hipError_t set_resident_lds_limit() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_resident<double>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_resident<float>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+  const void* fns[] = {(const void*)k_resident<double, false>, (const void*)k_resident<float, false>,
+                       (const void*)k_resident<double, true>, (const void*)k_resident<float, true>};
+  for (const void* f : fns) {
+    const hipError_t e =
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 int tile_width(int kind) { return kind == 0 ? 64 : 16; }
@@ -662,10 +677,15 @@ hipError_t launch_field(bool fp64, int kind, int G, const SysDesc* d_sys, const 
   return hipGetLastError();
 }
 
-hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks,
+hipError_t launch_update(bool scan, const SysDesc* d_sys, const int2* d_blocks, int nblocks,
                          const int64_t* kbase, int64_t koff, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_update, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase, koff);
+  if (scan)
+    hipLaunchKernelGGL(k_update<true>, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase,
+                       koff);
+  else
+    hipLaunchKernelGGL(k_update<false>, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase,
+                       koff);
   return hipGetLastError();
 }
 
@@ -727,9 +747,9 @@ hipError_t launch_philox_raw(uint64_t seed, uint64_t stream, const uint64_t* d_c
 }
 
 hipError_t launch_sw(const double* hx, const double* hy, const double* th0, double* out, int64_t n,
-                     hipStream_t st) {
+                     bool scan200, hipStream_t st) {
   hipLaunchKernelGGL(k_sw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, hx, hy, th0, out,
-                     n);
+                     n, scan200 ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -61,7 +61,8 @@ __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {
 
 // Steps iii-vii for particle i of system s with the reduced dipolar sum (ax, ay, az)
 // from the moments in buffer cur; writes buffer cur^1, accumulates the area, and
-// returns the new m_x.
+// returns the new m_x. kScan as for np_update.
+template <bool kScan>
 __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur, double ax, double ay,
                               double az) {
   if (s.field_only) {
@@ -85,7 +86,7 @@ __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur
   const D4 mo = s.m64[(int64_t)cur * s.stride + i];
   const D4 nn = s.axes[i];
   const NPResult r =
-      np_update(s.np, Bx, By, Bz, nn.x, nn.y, nn.z, mo.x, mo.y, mo.z, s.seed, s.stream, i, k);
+      np_update<kScan>(s.np, Bx, By, Bz, nn.x, nn.y, nn.z, mo.x, mo.y, mo.z, s.seed, s.stream, i, k);
   const int nxt = cur ^ 1;
   D4 mn;
   mn.x = r.mx;

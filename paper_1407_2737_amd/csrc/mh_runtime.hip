@@ -22,14 +22,14 @@
 #include "mh_kernels.hpp"
 
 namespace mh {
-hipError_t launch_resident(bool fp64, const SysDesc* d_sys, int nsys, int64_t k0, int64_t k1,
-                           int nmax, hipStream_t st);
+hipError_t launch_resident(bool fp64, bool scan, const SysDesc* d_sys, int nsys, int64_t k0,
+                           int64_t k1, int nmax, hipStream_t st);
 size_t resident_lds_bytes(bool fp64, int nmax);
 hipError_t set_resident_lds_limit();
 int tile_width(int kind);
 hipError_t launch_field(bool fp64, int kind, int G, const SysDesc* d_sys, const int4* d_tiles,
                         int ntiles, const int64_t* kbase, int64_t koff, hipStream_t st);
-hipError_t launch_update(const SysDesc* d_sys, const int2* d_blocks, int nblocks,
+hipError_t launch_update(bool scan, const SysDesc* d_sys, const int2* d_blocks, int nblocks,
                          const int64_t* kbase, int64_t koff, hipStream_t st);
 hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st);
 int wm_tile_rows();
@@ -39,7 +39,7 @@ int wm_ksplit();
 hipError_t launch_wm_build(const D4* pos, int n, __bf16* whi, __bf16* wlo, int Mp, int Kp,
                            hipStream_t st);
 hipError_t launch_wm_gemm(const WMArgs& g, hipStream_t st);
-hipError_t launch_wm_update(const SysDesc* d_sys, int R, int n, const WMArgs& g,
+hipError_t launch_wm_update(bool scan, const SysDesc* d_sys, int R, int n, const WMArgs& g,
                             const int64_t* kbase, int64_t koff, hipStream_t st);
 hipError_t launch_wm_pack(const SysDesc* d_sys, int R, int n, const WMArgs& g, int b,
                           hipStream_t st);
@@ -54,7 +54,7 @@ hipError_t launch_area_per_np(const double* d_area, int n, int R, int n_kept, do
 hipError_t launch_philox_raw(uint64_t seed, uint64_t stream, const uint64_t* d_ctr, uint64_t* d_out,
                              int64_t nblk, hipStream_t st);
 hipError_t launch_sw(const double* hx, const double* hy, const double* th0, double* out, int64_t n,
-                     hipStream_t st);
+                     bool scan200, hipStream_t st);
 }  // namespace mh
 
 using namespace mh;
@@ -195,7 +195,9 @@ int validate_params(const mh_params* p) {
   if (p->precision != MH_FP64 && p->precision != MH_FP32_FIELD && p->precision != MH_BF16X3_WM)
     return MH_EINVAL;
   if (p->interactions != 0 && p->interactions != 1) return MH_EINVAL;
-  if (p->reserved[0] || p->reserved[1]) return MH_EINVAL;
+  if (p->extrema_mode != MH_EXTREMA_EXACT && p->extrema_mode != MH_EXTREMA_SCAN200)
+    return MH_EINVAL;
+  if (p->reserved) return MH_EINVAL;
   return MH_OK;
 }
 
@@ -379,6 +381,7 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   const double dt = p.dt_override > 0 ? p.dt_override : 1.0 / (p.f * p.steps_per_period);
   s.np.nu0dt = dt / p.tau0;
   s.np.prob_form = p.prob_form;
+  s.np.scan200 = p.extrema_mode == MH_EXTREMA_SCAN200 ? 1 : 0;
   s.np.thermal = p.T > 0 ? 1 : 0;
   s.np.aniso = p.Keff > 0 ? 1 : 0;
   s.Bmax = a->hmax.empty() ? p.mu0Hmax : a->hmax[(size_t)(r % (int64_t)a->hmax.size())];
@@ -428,6 +431,9 @@ struct Plan {
   int nmax_res64 = 0, nmax_res32 = 0;
   int64_t kmax = 0;
   int nmax_all = 0;
+  // a system in the list takes step iv as the 200-point scan: launch the kernel
+  // instantiation that carries it
+  bool scan_res64 = false, scan_res32 = false, scan_upd = false;
 };
 
 // The R replicas of one tiled assembly: field blocks take up to 4 replicas at a time in
@@ -534,10 +540,12 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
         // handled by the matrix path below
       } else if (a->resident) {
         (fp64 ? pl.res64 : pl.res32).push_back(s);
+        (fp64 ? pl.scan_res64 : pl.scan_res32) |= s.np.scan200 != 0;
         int& nm = fp64 ? pl.nmax_res64 : pl.nmax_res32;
         nm = std::max(nm, (int)a->n);
       } else {
         reps.push_back(s);
+        pl.scan_upd |= s.np.scan200 != 0;
       }
       pl.kmax = std::max<int64_t>(pl.kmax, s.k_origin + s.total_steps);
       pl.nmax_all = std::max(pl.nmax_all, (int)a->n);
@@ -592,10 +600,11 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   const bool any_res = !pl.res64.empty() || !pl.res32.empty();
   bool any_til = !pl.wm.empty() || !pl.ublocks.empty();
   int tq = any_res && k1 > k0 ? timing_begin(c, st, 1) : -1;
-  if (launch_resident(true, d_res64, (int)pl.res64.size(), k0, k1, pl.nmax_res64, st) != hipSuccess)
+  if (launch_resident(true, pl.scan_res64, d_res64, (int)pl.res64.size(), k0, k1, pl.nmax_res64,
+                      st) != hipSuccess)
     return MH_EDEVICE;
-  if (launch_resident(false, d_res32, (int)pl.res32.size(), k0, k1, pl.nmax_res32, st) !=
-      hipSuccess)
+  if (launch_resident(false, pl.scan_res32, d_res32, (int)pl.res32.size(), k0, k1, pl.nmax_res32,
+                      st) != hipSuccess)
     return MH_EDEVICE;
   timing_end(c, st, tq);
   // one tiled step: dipolar fields, then the per-particle update
@@ -611,7 +620,8 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
         }
     timing_end(c, st, t0);
     t0 = timing_begin(c, st, 3);
-    if (launch_update(d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st) != hipSuccess)
+    if (launch_update(pl.scan_upd, d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st) !=
+        hipSuccess)
       return MH_EDEVICE;
     timing_end(c, st, t0);
     for (auto& it : pl.wm) {
@@ -619,7 +629,8 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       if (launch_wm_gemm(it.g, st) != hipSuccess) return MH_EDEVICE;
       timing_end(c, st, t0);
       t0 = timing_begin(c, st, 4);
-      if (launch_wm_update(d_all + it.first, (int)it.a->R, (int)it.a->n, it.g, kb, koff, st) !=
+      if (launch_wm_update(it.a->p.extrema_mode == MH_EXTREMA_SCAN200, d_all + it.first,
+                           (int)it.a->R, (int)it.a->n, it.g, kb, koff, st) !=
           hipSuccess)
         return MH_EDEVICE;
       timing_end(c, st, t0);
@@ -640,11 +651,13 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     }
     key.push_back((uint64_t)(uintptr_t)d_upd);
     key.push_back(pl.ublocks.size());
+    key.push_back(pl.scan_upd ? 1 : 0);
     for (auto& it : pl.wm) {
       const uint64_t* gw = reinterpret_cast<const uint64_t*>(&it.g);
       for (size_t q = 0; q < sizeof(WMArgs) / 8; ++q) key.push_back(gw[q]);
       key.push_back((uint64_t)it.first);
       key.push_back((uint64_t)it.a->R);
+      key.push_back((uint64_t)it.a->p.extrema_mode);
     }
     if (!c->gexec || key != c->gkey) {
       if (c->gexec) {
@@ -751,7 +764,8 @@ extern "C" {
 
 int mh_run_mean_loop(mh_asm* a, int64_t n_replicas, void* hip_stream) {
   if (!a || n_replicas < 1 || n_replicas > 65535) return MH_EINVAL;
-  if (a->p.interactions != 0 || !(a->p.Keff > 0)) return MH_EINVAL;
+  if (a->p.interactions != 0 || !(a->p.Keff > 0) || a->p.extrema_mode != MH_EXTREMA_EXACT)
+    return MH_EINVAL;
   return run_mean_loop(a, n_replicas, (hipStream_t)hip_stream);
 }
 
@@ -1416,7 +1430,13 @@ int mh_debug_philox(mh_ctx* c, uint64_t seed, uint64_t stream, int64_t n_blocks,
 
 int mh_debug_sw(mh_ctx* c, int64_t n, const double* hx, const double* hy, const double* theta0,
                 double* out) {
+  return mh_debug_sw_mode(c, MH_EXTREMA_EXACT, n, hx, hy, theta0, out);
+}
+
+int mh_debug_sw_mode(mh_ctx* c, int32_t extrema_mode, int64_t n, const double* hx,
+                     const double* hy, const double* theta0, double* out) {
   if (!c || !hx || !hy || !theta0 || !out || n < 1 || n > (1 << 26)) return MH_EINVAL;
+  if (extrema_mode != MH_EXTREMA_EXACT && extrema_mode != MH_EXTREMA_SCAN200) return MH_EINVAL;
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || !(hy[i] >= 0) ||
         !(std::fabs(theta0[i]) <= 3.14159265358979323846))
@@ -1429,7 +1449,8 @@ int mh_debug_sw(mh_ctx* c, int64_t n, const double* hx, const double* hy, const 
   if (hipMemcpy(d, hx, in, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d + n, hy, in, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d + 2 * n, theta0, in, hipMemcpyHostToDevice) != hipSuccess ||
-      launch_sw(d, d + n, d + 2 * n, d + 3 * n, n, c->stream) != hipSuccess ||
+      launch_sw(d, d + n, d + 2 * n, d + 3 * n, n, extrema_mode == MH_EXTREMA_SCAN200,
+                c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess ||
       hipMemcpy(out, d + 3 * n, in * 6, hipMemcpyDeviceToHost) != hipSuccess)
     rc = MH_EDEVICE;

@@ -234,6 +234,7 @@ __global__ void k_wm_pack(const SysDesc* __restrict__ systems, WMArgs g, int b) 
 // Per-particle update of the matrix form: thread (r, i) reads its three reduced field
 // components from B^T, runs steps iii-vii and writes the new moment (FP64 state and the
 // hi/lo split for the next product).
+template <bool kScan>
 __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ systems, WMArgs g,
                                                    const int64_t* __restrict__ kbase,
                                                    int64_t koff) {
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ s
       fy += (double)f[1];
       fz += (double)f[2];
     }
-    mx = np_epilogue(s, i, k, cur, fx, fy, fz);
+    mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz);
     if (!s.field_only) {
       const D4 m = s.m64[(int64_t)(cur ^ 1) * s.stride + i];
       store_split(g, r, i, m.x, m.y, m.z);
@@ -292,10 +293,14 @@ hipError_t launch_wm_gemm(const WMArgs& g, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_wm_update(const SysDesc* d_sys, int R, int n, const WMArgs& g,
+hipError_t launch_wm_update(bool scan, const SysDesc* d_sys, int R, int n, const WMArgs& g,
                             const int64_t* kbase, int64_t koff, hipStream_t st) {
-  hipLaunchKernelGGL(k_wm_update, dim3((n + 255) / 256, R), dim3(256), 0, st, d_sys, g, kbase,
-                     koff);
+  if (scan)
+    hipLaunchKernelGGL(k_wm_update<true>, dim3((n + 255) / 256, R), dim3(256), 0, st, d_sys, g,
+                       kbase, koff);
+  else
+    hipLaunchKernelGGL(k_wm_update<false>, dim3((n + 255) / 256, R), dim3(256), 0, st, d_sys, g,
+                       kbase, koff);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #define __device__
 #define __host__
 #define __forceinline__ inline
+#define __noinline__ __attribute__((noinline))
 #define HIP_INCLUDE_HIP_HIP_RUNTIME_H
 static inline uint64_t __umul64hi(uint64_t a, uint64_t b) {
   return (uint64_t)(((__uint128_t)a * b) >> 64);
@@ -22,6 +23,9 @@ static inline void host_sincosf(float t, float* s, float* c) {
 using std::fabs;
 using std::fmax;
 using std::copysign;
+using std::isnan;
+using std::remainder;
+using std::fmin;
 #include "../../paper_1407_2737_amd/csrc/mh_device.hpp"
 
 extern "C" {
@@ -51,10 +55,26 @@ void dl_sw(int64_t n, const double* hx, const double* hy, const double* th0, dou
   }
 }
 
+// As dl_sw with step iv as the 200-point scan.
+void dl_sw_scan200(int64_t n, const double* hx, const double* hy, const double* th0,
+                   double* out) {
+  for (int64_t i = 0; i < n; ++i) {
+    const mh::Dir d = {std::sin(th0[i]), std::cos(th0[i])};
+    const mh::SWState r = mh::sw_fall_scan200(hx[i], hy[i], d);
+    double* o = out + 6 * i;
+    o[0] = std::atan2(r.s_c, r.c_c);
+    o[1] = r.e_c;
+    o[2] = std::atan2(r.s_o, r.c_o);
+    o[3] = r.e_o;
+    o[4] = r.e3;
+    o[5] = r.two ? 1.0 : 0.0;
+  }
+}
+
 // B, n, m: n x 3; out: n x 6 (new moment, P, jump, two)
 void dl_update(int64_t n, const double* B, const double* ax, const double* m, double BK,
                double beta, double nu0dt, int prob_form, int thermal, uint64_t seed,
-               uint64_t stream, int64_t k, double* out) {
+               uint64_t stream, int64_t k, int scan200, double* out) {
   mh::NPParams p;
   p.BK = BK;
   p.BK_inv = 1.0 / BK;
@@ -63,9 +83,10 @@ void dl_update(int64_t n, const double* B, const double* ax, const double* m, do
   p.prob_form = prob_form;
   p.thermal = thermal;
   p.aniso = 1;
+  p.scan200 = scan200;
   for (int64_t i = 0; i < n; ++i) {
     const mh::NPResult r =
-        mh::np_update(p, B[3 * i], B[3 * i + 1], B[3 * i + 2], ax[3 * i], ax[3 * i + 1],
+        mh::np_update<true>(p, B[3 * i], B[3 * i + 1], B[3 * i + 2], ax[3 * i], ax[3 * i + 1],
                       ax[3 * i + 2], m[3 * i], m[3 * i + 1], m[3 * i + 2], seed, stream, i, k);
     double* o = out + 6 * i;
     o[0] = r.mx;
@@ -92,6 +113,7 @@ void dl_master(int64_t n, const double* ax, double Ms, double BK, double beta, d
   p.prob_form = prob_form;
   p.thermal = thermal;
   p.aniso = 1;
+  p.scan200 = 0;
   std::vector<mh::MasterState> q((size_t)n);
   std::vector<double> prev((size_t)n), sum((size_t)n, 0.0), comp((size_t)n, 0.0);
   for (int64_t i = 0; i < n; ++i) {

@@ -33,8 +33,9 @@ def dl():
     u64p = C.POINTER(C.c_uint64)
     L.dl_philox.argtypes = [C.c_uint64, C.c_uint64, C.c_int64, u64p, u64p]
     L.dl_sw.argtypes = [C.c_int64, dp, dp, dp, dp]
+    L.dl_sw_scan200.argtypes = [C.c_int64, dp, dp, dp, dp]
     L.dl_update.argtypes = [C.c_int64, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
-                            C.c_int, C.c_uint64, C.c_uint64, C.c_int64, dp]
+                            C.c_int, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, dp]
     L.dl_master.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                             C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
                             dp, dp]
@@ -84,12 +85,47 @@ def test_sw_fall_matches_oracle(dl):
     assert np.abs(out[two, 4] - e3[two]).max() < 1e-12
 
 
-@pytest.mark.parametrize("prob_form", [0, 1])
-def test_update_matches_oracle_step(dl, prob_form):
+def test_sw_fall_scan200_matches_oracle(dl):
+    """The paper-literal search (200-point scan + Newton) against the oracle's, over
+    the same field mix as above: pair counts decided identically, including the pairs
+    the scan misses next to the astroid, which fall back to the one stable well."""
+    rng = np.random.default_rng(16)
+    n = 20000
+    h = rng.uniform(0, 2.0, n) ** 1.5
+    phi = rng.uniform(0, np.pi, n)
+    hx, hy = h * np.cos(phi), h * np.sin(phi)
+    hx[:300] = rng.uniform(-1.5, 1.5, 300)
+    hy[:300] = 0.0
+    hx[300:600] = 0.0
+    hy[300:600] = rng.uniform(0, 1.5, 300)
+    psi = rng.uniform(0.05, np.pi / 2 - 0.05, 1000)
+    hsw = (np.cos(psi) ** (2 / 3) + np.sin(psi) ** (2 / 3)) ** -1.5
+    hh = hsw * (1 - 10 ** rng.uniform(-7, -1, 1000))
+    hx[600:1600], hy[600:1600] = hh * np.cos(psi), hh * np.sin(psi)
+    th0 = rng.uniform(-np.pi, np.pi, n)
+    out = np.empty((n, 6))
+    dl.dl_sw_scan200(n, _p(hx), _p(hy), _p(th0), _p(out))
+    th, mn, cnt = sw.stationary_points_scan200(hx, hy)
+    tc, ec, to, eo, e3, two = sw.classify(th0, th, mn, cnt, hx, hy)
+    _, _, cnt_exact = sw.stationary_points(hx, hy)
+    missed = (cnt_exact == 4) & (cnt == 2)
+    assert missed[600:1600].sum() > 100          # the scan's known loss near h_sw
+    assert np.array_equal(out[:, 5] == 1.0, two)
+    dc = np.abs(np.angle(np.exp(1j * (out[:, 0] - tc))))
+    assert dc.max() < 1e-12, dc.max()
+    do = np.abs(np.angle(np.exp(1j * (out[:, 2] - to))))
+    assert do[two].max() < 1e-12, do[two].max()
+    assert np.abs(out[:, 1] - ec).max() < 1e-12
+    assert np.abs(out[two, 3] - eo[two]).max() < 1e-12
+    assert np.abs(out[two, 4] - e3[two]).max() < 1e-12
+
+
+@pytest.mark.parametrize("prob_form,scan", [(0, 0), (1, 0), (0, 1)])
+def test_update_matches_oracle_step(dl, prob_form, scan):
     rng = np.random.default_rng(7 + prob_form)
     n = 4000
     p = kmc.Params(Ms=4e5, Keff=1.3e4, d=12e-9, T=300.0, mu0Hmax=0.02, interactions=0,
-                   prob_form=prob_form)
+                   prob_form=prob_form, extrema_mode=scan)
     dv = kmc.derived(p)
     axes = rng.normal(size=(n, 3))
     axes /= np.linalg.norm(axes, axis=1, keepdims=True)
@@ -100,7 +136,7 @@ def test_update_matches_oracle_step(dl, prob_form):
     m_new, info = kmc.step(np.zeros((n, 3)), axes, m, k, p, 4321, 3, B_override=B)
     out = np.empty((n, 6))
     dl.dl_update(n, _p(B), _p(axes), _p(m), dv["BK"], dv["beta"], dv["nu0dt"], prob_form, 1,
-                 4321, 3, k, _p(out))
+                 4321, 3, k, scan, _p(out))
     assert np.array_equal(out[:, 5] == 1.0, info.two)
     assert np.array_equal(out[:, 4] == 1.0, info.jump)
     assert np.abs(out[:, 3] - info.P).max() < 1e-12
