@@ -4,23 +4,25 @@ steps i-viii, Eqs. 1-5; loop protocol Sec. III.1; SAR conversion Sec. III.2.a).
 Readings of points the paper leaves open (applied identically by the GPU library):
 
 * Eq. 1 sums over the other particles j != i; the result mu0 H_dip is in tesla.
-* Field H_k = H_max cos(2 pi k / S) along x, constant during step k (steps of equal
-  length dt = 1/(f S)); a run is n_periods periods starting at +H_max; the first
-  n_discard periods are thrown away (Sec. III.1).
+* Field H_k = H_max cos(2 pi k / S) along a fixed unit direction e_H (x unless
+  field_dir says otherwise; (0, 0, 0) means x), constant during step k (steps of
+  equal length dt = 1/(f S)); a run is n_periods periods starting at +H_max; the first
+  n_discard periods are thrown away (Sec. III.1). Loop, area and Eq. 6 use the
+  components along e_H, which is x in the paper.
 * Working plane (step iii): u1 = easy axis n, u2 = the unit part of B_tot normal to
   n. When that part vanishes (|B_perp| <= 1e-12 max(|B|, mu0 H_K)) u2 is the unit
   part of the previous moment normal to n, else the normalised n x e, with e the
   coordinate axis least aligned with n.
-* Initial moments m_i = sign(n_i . x) n_i with sign(0) = +1.
+* Initial moments m_i = sign(n_i . e_H) n_i with sign(0) = +1.
 * Eq. 5 is read as the probability to leave the current well c for the other well o:
   P = nu_c/(nu_c+nu_o) (1 - exp(-(nu_c+nu_o) dt)), nu = nu0 exp(-(E3-E)/kT); it is
   evaluated as sigma(a_o - a_c) * (-expm1(-nu0 dt (e^-a_c + e^-a_o))), which is the
   same expression rearranged so that it cannot overflow. Jump iff u < P.
   prob_form=1 selects the single-rate form 1 - exp(-nu_c dt) instead.
 * T = 0: steps vi-vii are skipped; K_eff = 0: the moment aligns with B_tot.
-* Area: A = M_S sum_k mu0H_k (m_x,k - m_x,k-1) over the kept steps (work done at
-  constant field per step), J/m^3; SAR = A f / rho.
-* Eq. 6: the dipolar field "at +mu0 H_max" (-mu0 H_max) is the x component of the Eq. 1
+* Area: A = M_S sum_k mu0H_k (m_H,k - m_H,k-1) over the kept steps (work done at
+  constant field per step; m_H = m . e_H), J/m^3; SAR = A f / rho.
+* Eq. 6: the dipolar field "at +mu0 H_max" (-mu0 H_max) is the e_H component of the Eq. 1
   field acting in the step whose applied field is +H_max (-H_max), k = 0 (S/2) mod S,
   i.e. computed from that step's start-of-step moments; Delta-_Hdip per particle is
   its difference, averaged over the kept periods.
@@ -55,6 +57,7 @@ class Params:
     prob_form: int = 0
     interactions: int = 1
     extrema_mode: int = 0    # 0: exact stationary points; 1: the paper's 200-point scan
+    field_dir: tuple = (1.0, 0.0, 0.0)   # direction of the applied field
 
     @classmethod
     def from_dict(cls, d):
@@ -72,8 +75,15 @@ def derived(p: Params):
     return dict(V=V, C=C, BK=BK, beta=beta, dt=dt, nu0dt=dt / p.tau0)
 
 
+def field_unit(p: Params) -> np.ndarray:
+    """The unit direction e_H of the applied field: field_dir normalised, x for (0, 0, 0)."""
+    d = np.asarray(p.field_dir, dtype=np.float64)
+    nd = np.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+    return np.array([1.0, 0.0, 0.0]) if nd == 0.0 else d / nd
+
+
 def applied_field(k: int, p: Params) -> float:
-    """mu0 H_ext at step k (x component), Sec. II.1 and Sec. III.1."""
+    """mu0 H_ext at step k (its component along e_H), Sec. II.1 and Sec. III.1."""
     if p.dt_override > 0:
         return p.mu0Hmax
     return p.mu0Hmax * np.cos(2.0 * np.pi * k / p.steps_per_period)
@@ -169,7 +179,7 @@ def step(pos, axes, m, k, p: Params, seed: int, stream: int, B_override=None):
         if p.interactions and n > 1:
             B += dipolar_field(pos, m, dv["C"])
         Bdip = B.copy()
-        B[:, 0] += Bx
+        B += Bx * field_unit(p)[None, :]
     if p.Keff <= 0:
         Bn = np.linalg.norm(B, axis=1)
         m_new = np.where(Bn[:, None] > 0, B / np.where(Bn > 0, Bn, 1.0)[:, None], m)
@@ -198,15 +208,17 @@ def step(pos, axes, m, k, p: Params, seed: int, stream: int, B_override=None):
     return m_new, info
 
 
-def initial_moments(axes: np.ndarray) -> np.ndarray:
-    s = np.where(axes[:, 0] >= 0.0, 1.0, -1.0)
+def initial_moments(axes: np.ndarray, e_H=(1.0, 0.0, 0.0)) -> np.ndarray:
+    """m_i = sign(n_i . e_H) n_i, sign(0) = +1: saturated along the field at +H_max."""
+    e = np.asarray(e_H, dtype=np.float64)
+    s = np.where(axes @ e >= 0.0, 1.0, -1.0)
     return axes * s[:, None]
 
 
 @dataclass
 class LoopResult:
     H: np.ndarray                  # (S,) mu0 H_k, tesla
-    M: np.ndarray                  # (n_kept, S) M_S <m_x> after each step, A/m
+    M: np.ndarray                  # (n_kept, S) M_S <m . e_H> after each step, A/m
     area_per_np: np.ndarray        # (N,) J/m^3, mean over kept periods
     area: float                    # J/m^3
     sar: float                     # W/kg
@@ -223,7 +235,8 @@ def simulate(pos, axes, p: Params, seed: int, stream: int = 0, n_steps: int | No
     total = p.n_periods * S if n_steps is None else n_steps
     kept0 = p.n_discard * S
     n_kept = max(0, p.n_periods - p.n_discard)
-    m = initial_moments(axes) if m0 is None else np.array(m0, dtype=np.float64)
+    eH = field_unit(p)
+    m = initial_moments(axes, eH) if m0 is None else np.array(m0, dtype=np.float64)
     n = pos.shape[0]
     area = np.zeros(n)
     dhdip = np.zeros(n)
@@ -235,11 +248,12 @@ def simulate(pos, axes, p: Params, seed: int, stream: int = 0, n_steps: int | No
         m_new, info = step(pos, axes, m, k, p, seed, stream)
         jumps += int(info.jump.sum())
         if k >= kept0 and info.Bdip is not None and k % S in (0, S // 2):
-            # Eq. 6: dipolar field along x at +H_max minus at -H_max
-            dhdip += info.Bdip[:, 0] if k % S == 0 else -info.Bdip[:, 0]
+            # Eq. 6: dipolar field along e_H at +H_max minus at -H_max
+            bh = info.Bdip @ eH
+            dhdip += bh if k % S == 0 else -bh
         if k >= kept0:
-            area += p.Ms * applied_field(k, p) * (m_new[:, 0] - m[:, 0])
-            Mrec[(k - kept0) // S, k % S] = p.Ms * m_new[:, 0].mean()
+            area += p.Ms * applied_field(k, p) * (m_new @ eH - m @ eH)
+            Mrec[(k - kept0) // S, k % S] = p.Ms * (m_new @ eH).mean()
         if keep_trace:
             trace.append(info)
         m = m_new

@@ -27,7 +27,7 @@ def _fall(B, axes, mvec, BK):
 
 
 def mean_loop(axes: np.ndarray, p: kmc.Params):
-    """Returns (H (S,), M (n_kept, S) expected M_S <m_x>, expected area J/m^3)."""
+    """Returns (H (S,), M (n_kept, S) expected M_S <m . e_H>, expected area J/m^3)."""
     if p.interactions:
         raise ValueError("the mean-magnetisation loop is defined for non-interacting particles")
     dv = kmc.derived(p)
@@ -36,18 +36,18 @@ def mean_loop(axes: np.ndarray, p: kmc.Params):
     total = p.n_periods * S
     kept0 = p.n_discard * S
     n_kept = p.n_periods - p.n_discard
-    mA = kmc.initial_moments(axes)
+    eH = kmc.field_unit(p)
+    mA = kmc.initial_moments(axes, eH)
     wA = np.ones(n)
     mB = mA.copy()
     wB = np.zeros(n)
     Mrec = np.zeros((n_kept, S))
     Hrec = np.array([kmc.applied_field(k, p) for k in range(S)])
     area = 0.0
-    mx_prev = (wA * mA[:, 0] + wB * mB[:, 0]).mean()
+    mx_prev = (wA * (mA @ eH) + wB * (mB @ eH)).mean()
     for k in range(total):
         Bx = kmc.applied_field(k, p)
-        B = np.zeros((n, 3))
-        B[:, 0] = Bx
+        B = np.zeros((n, 3)) + Bx * eH[None, :]
         uA, thcA, ecA, thoA, eoA, e3A, two = _fall(B, axes, mA, dv["BK"])
         uB, thcB, ecB, thoB, eoB, e3B, _ = _fall(B, axes, mB, dv["BK"])
         # both weighted vectors live in the same plane unless it is degenerate; the
@@ -78,7 +78,7 @@ def mean_loop(axes: np.ndarray, p: kmc.Params):
         mA = np.cos(t1)[:, None] * axes + np.sin(t1)[:, None] * uA
         mB = np.cos(t2)[:, None] * axes + np.sin(t2)[:, None] * uA
         wA, wB = w1, w2
-        mx = (wA * mA[:, 0] + wB * mB[:, 0]).mean()
+        mx = (wA * (mA @ eH) + wB * (mB @ eH)).mean()
         if k >= kept0:
             area += p.Ms * Bx * (mx - mx_prev)
             Mrec[(k - kept0) // S, k % S] = p.Ms * mx
