@@ -79,8 +79,12 @@ typedef struct {
   double tau0;        /* inverse attempt frequency 1/nu0, s (> 0; paper: 1e-10) */
   double rho;         /* density for SAR, kg/m^3 (> 0; paper: 5200) */
   double f;           /* field frequency, Hz (> 0) */
-  double mu0Hmax;     /* field amplitude, T (>= 0); field along +x, H_k = Hmax cos(2 pi k/S) */
-  double dt_override; /* > 0: constant field mu0Hmax along x and steps of this length, s */
+  double mu0Hmax;     /* field amplitude, T (>= 0); H_k = Hmax cos(2 pi k/S) e_H */
+  double dt_override; /* > 0: constant field mu0Hmax e_H and steps of this length, s */
+  double field_dir[3];/* direction of the applied field, normalised to e_H; (0, 0, 0) means
+                         +x, the paper's choice (Sec. II.1). Moments start as
+                         sign(n . e_H) n; loops (mh_get_loop), areas, SAR and Eq. 6
+                         (mh_get_dhdip) use the components along e_H */
   int32_t steps_per_period; /* S, even, >= 2 (paper: 2000) */
   int32_t n_periods;        /* periods run (>= 1) */
   int32_t n_discard;        /* leading periods not kept (0 <= n_discard < n_periods) */

@@ -43,7 +43,7 @@ class Params(C.Structure):
     _fields_ = [("Ms", C.c_double), ("Keff", C.c_double), ("d", C.c_double), ("T", C.c_double),
                 ("tau0", C.c_double), ("rho", C.c_double), ("f", C.c_double),
                 ("mu0Hmax", C.c_double), ("dt_override", C.c_double),
-                ("steps_per_period", C.c_int32), ("n_periods", C.c_int32),
+                ("field_dir", C.c_double * 3), ("steps_per_period", C.c_int32), ("n_periods", C.c_int32),
                 ("n_discard", C.c_int32), ("prob_form", C.c_int32), ("precision", C.c_int32),
                 ("interactions", C.c_int32), ("extrema_mode", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -53,10 +53,11 @@ class Params(C.Structure):
         p = cls()
         defaults = dict(Ms=4.0e5, Keff=1.3e4, d=12e-9, T=300.0, tau0=1e-10, rho=5200.0, f=1e5,
                         mu0Hmax=0.02, dt_override=0.0, steps_per_period=2000, n_periods=3,
-                        n_discard=2, prob_form=0, interactions=1, extrema_mode=0)
+                        n_discard=2, prob_form=0, interactions=1, extrema_mode=0,
+                        field_dir=(1.0, 0.0, 0.0))
         defaults.update({k: v for k, v in kw.items() if k in defaults})
         for k, v in defaults.items():
-            setattr(p, k, v)
+            setattr(p, k, (C.c_double * 3)(*v) if k == "field_dir" else v)
         p.precision = precision
         return p
 

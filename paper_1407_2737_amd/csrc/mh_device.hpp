@@ -681,8 +681,9 @@ struct MasterState {
   double ax, ay, az, bx, by, bz, wa, wb;
 };
 
-__device__ __forceinline__ void master_init(MasterState& q, double nx, double ny, double nz) {
-  const double sg = nx >= 0.0 ? 1.0 : -1.0;
+__device__ __forceinline__ void master_init(MasterState& q, double nx, double ny, double nz,
+                                            double ex, double ey, double ez) {
+  const double sg = nx * ex + ny * ey + nz * ez >= 0.0 ? 1.0 : -1.0;
   q.ax = q.bx = sg * nx;
   q.ay = q.by = sg * ny;
   q.az = q.bz = sg * nz;
@@ -690,18 +691,20 @@ __device__ __forceinline__ void master_init(MasterState& q, double nx, double ny
   q.wb = 0.0;
 }
 
-// One step in the applied field Bext (along x): both weighted moments fall (steps
-// iii-v; B uses A's plane unless the field lies along the axis, where the plane follows
-// each moment and the minima are +-n), weights reaching the same minimum are pooled,
-// Eq. 5 moves w_c P(c->o) from each well to the other (steps vi-vii), and with one
-// minimum all weight goes to it. Requires K > 0. Returns the expected m_x.
-__device__ __forceinline__ double master_step(const NPParams& p, double Bext, double nx,
-                                              double ny, double nz, MasterState& q) {
-  const Plane pa = working_plane(p, Bext, 0.0, 0.0, nx, ny, nz, q.ax, q.ay, q.az);
+// One step in the applied field Bext e_H: both weighted moments fall (steps iii-v; B
+// uses A's plane unless the field lies along the axis, where the plane follows each
+// moment and the minima are +-n), weights reaching the same minimum are pooled, Eq. 5
+// moves w_c P(c->o) from each well to the other (steps vi-vii), and with one minimum
+// all weight goes to it. Requires K > 0. Returns the expected moment along e_H.
+__device__ __forceinline__ double master_step(const NPParams& p, double Bext, double ex,
+                                              double ey, double ez, double nx, double ny,
+                                              double nz, MasterState& q) {
+  const double Bx = Bext * ex, By = Bext * ey, Bz = Bext * ez;
+  const Plane pa = working_plane(p, Bx, By, Bz, nx, ny, nz, q.ax, q.ay, q.az);
   const SWState fa = sw_fall(pa.hx, pa.hy, pa.d0);
   Plane pb = pa;
   if (pa.deg)
-    pb = working_plane(p, Bext, 0.0, 0.0, nx, ny, nz, q.bx, q.by, q.bz);
+    pb = working_plane(p, Bx, By, Bz, nx, ny, nz, q.bx, q.by, q.bz);
   else
     pb.d0 = dir_of(q.bx * pa.ux + q.by * pa.uy + q.bz * pa.uz, q.bx * nx + q.by * ny + q.bz * nz);
   const SWState fb = sw_fall(pb.hx, pb.hy, pb.d0);
@@ -727,7 +730,7 @@ __device__ __forceinline__ double master_step(const NPParams& p, double Bext, do
   q.bz = fa.c_o * nz + fa.s_o * pa.uz;
   q.wa = w1;
   q.wb = w2;
-  return w1 * q.ax + w2 * q.bx;
+  return w1 * (q.ax * ex + q.ay * ey + q.az * ez) + w2 * (q.bx * ex + q.by * ey + q.bz * ez);
 }
 
 // Neumaier compensated accumulation: sum += x with running compensation.

@@ -449,12 +449,13 @@ __global__ __launch_bounds__(256) void k_master(const SysDesc* __restrict__ syst
   const int i = blockIdx.x * 256 + threadIdx.x;
   const bool act = i < s.n;
   const D4 nn = s.axes[act ? i : s.n - 1];  // idle lanes shadow the last particle
+  const double ex = s.eh[0], ey = s.eh[1], ez = s.eh[2];
   MasterState q;
-  master_init(q, nn.x, nn.y, nn.z);
-  double mx_prev = q.ax, sum = 0.0, comp = 0.0;
+  master_init(q, nn.x, nn.y, nn.z, ex, ey, ez);
+  double mx_prev = q.ax * ex + q.ay * ey + q.az * ez, sum = 0.0, comp = 0.0;
   for (int k = 0; k < s.total_steps; ++k) {
     const double Bext = applied_field(s, k);
-    const double mx = master_step(s.np, Bext, nn.x, nn.y, nn.z, q);
+    const double mx = master_step(s.np, Bext, ex, ey, ez, nn.x, nn.y, nn.z, q);
     if (k >= s.kept0) {
       neumaier_add(sum, comp, s.Ms * Bext * (mx - mx_prev));
       const double t = block_sum_256(act ? mx : 0.0, red);
@@ -526,7 +527,7 @@ __global__ void k_init(const SysDesc* __restrict__ systems) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < s.n) {
     const D4 a = s.axes[i];
-    const double sg = a.x >= 0.0 ? 1.0 : -1.0;
+    const double sg = a.x * s.eh[0] + a.y * s.eh[1] + a.z * s.eh[2] >= 0.0 ? 1.0 : -1.0;
     D4 m;
     m.x = sg * a.x;
     m.y = sg * a.y;

@@ -34,6 +34,7 @@ struct SysDesc {
   NPParams np;
   double Bmax;       // mu0 Hmax (T)
   double Bscale;     // mu0 Ms / 24: field unit of the reduced dipolar sum (T)
+  double eh[3];      // unit direction of the applied field
   double Ms;
   int32_t n;
   int32_t ntiles;    // update blocks of 256 particles (1 for the resident kernel)
@@ -61,7 +62,8 @@ __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {
 
 // Steps iii-vii for particle i of system s with the reduced dipolar sum (ax, ay, az)
 // from the moments in buffer cur; writes buffer cur^1, accumulates the area, and
-// returns the new m_x. kScan as for np_update.
+// returns the new moment's component along the field direction e_H. kScan as for
+// np_update.
 template <bool kScan>
 __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur, double ax, double ay,
                               double az) {
@@ -73,15 +75,18 @@ __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur
     return 0.0;
   }
   const double Bext = applied_field(s, k);
-  const double Bx = Bext + s.Bscale * ax, By = s.Bscale * ay, Bz = s.Bscale * az;
+  const double ex = s.eh[0], ey = s.eh[1], ez = s.eh[2];
+  const double Bx = s.Bscale * ax + Bext * ex, By = s.Bscale * ay + Bext * ey,
+               Bz = s.Bscale * az + Bext * ez;
   if (s.dhdip && k >= s.kept0) {
-    // Eq. 6: the dipolar field along x in the +Hmax step (k = 0 mod S) minus that in
+    // Eq. 6: the dipolar field along e_H in the +Hmax step (k = 0 mod S) minus that in
     // the -Hmax step (k = S/2 mod S)
     const int64_t ph = k % s.S;
+    const double bh = s.Bscale * ax * ex + s.Bscale * ay * ey + s.Bscale * az * ez;
     if (ph == 0)
-      s.dhdip[i] += s.Bscale * ax;
+      s.dhdip[i] += bh;
     else if (ph == s.S / 2)
-      s.dhdip[i] -= s.Bscale * ax;
+      s.dhdip[i] -= bh;
   }
   const D4 mo = s.m64[(int64_t)cur * s.stride + i];
   const D4 nn = s.axes[i];
@@ -102,9 +107,11 @@ __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur
     mf.w = 0.f;
     s.m32[(int64_t)nxt * s.stride + i] = mf;
   }
+  const double mh_new = r.mx * ex + r.my * ey + r.mz * ez;
   if (k >= s.kept0) {
+    const double mh_old = mo.x * ex + mo.y * ey + mo.z * ez;
     double sum = s.area[i], comp = s.area[s.n + i];
-    neumaier_add(sum, comp, s.Ms * Bext * (r.mx - mo.x));
+    neumaier_add(sum, comp, s.Ms * Bext * (mh_new - mh_old));
     s.area[i] = sum;
     s.area[s.n + i] = comp;
   }
@@ -119,7 +126,7 @@ __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur
     d[6] = 0.0;
     d[7] = 0.0;
   }
-  return r.mx;
+  return mh_new;
 }
 
 }  // namespace mh

@@ -181,8 +181,9 @@ int n_kept(const mh_params& p) { return p.n_periods - p.n_discard; }
 
 int validate_params(const mh_params* p) {
   if (!p) return MH_EINVAL;
-  const double v[] = {p->Ms, p->Keff, p->d, p->T, p->tau0, p->rho, p->f, p->mu0Hmax,
-                      p->dt_override};
+  const double v[] = {p->Ms,      p->Keff,         p->d,           p->T,
+                      p->tau0,    p->rho,          p->f,           p->mu0Hmax,
+                      p->dt_override, p->field_dir[0], p->field_dir[1], p->field_dir[2]};
   for (double x : v)
     if (!std::isfinite(x)) return MH_EINVAL;
   if (p->Ms <= 0 || p->Keff < 0 || p->d <= 0 || p->T < 0 || p->tau0 <= 0 || p->rho <= 0 ||
@@ -386,6 +387,13 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.np.aniso = p.Keff > 0 ? 1 : 0;
   s.Bmax = a->hmax.empty() ? p.mu0Hmax : a->hmax[(size_t)(r % (int64_t)a->hmax.size())];
   s.Bscale = p.interactions ? kMu0 * p.Ms / 24.0 : 0.0;
+  {
+    const double* e = p.field_dir;
+    const double en = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    s.eh[0] = en == 0.0 ? 1.0 : e[0] / en;
+    s.eh[1] = en == 0.0 ? 0.0 : e[1] / en;
+    s.eh[2] = en == 0.0 ? 0.0 : e[2] / en;
+  }
   s.Ms = p.Ms;
   s.n = (int32_t)n;
   s.ntiles = a->ntiles;

@@ -99,12 +99,12 @@ void dl_update(int64_t n, const double* B, const double* ax, const double* m, do
 }
 
 // Mean-magnetisation loop of n non-interacting particles, as the GPU kernel runs it:
-// per step every particle's master_step, then the loop record (M_S <m_x> for each
+// per step every particle's master_step, then the loop record (M_S <m . e_H> for each
 // kept step, n_kept x S) and the per-particle compensated area averaged over particles
-// and kept periods (area_out[0], J/m^3).
+// and kept periods (area_out[0], J/m^3). eh: unit field direction.
 void dl_master(int64_t n, const double* ax, double Ms, double BK, double beta, double nu0dt,
                int prob_form, int thermal, double Bmax, int S, int n_periods, int n_discard,
-               int static_field, double* M_out, double* area_out) {
+               int static_field, const double* eh, double* M_out, double* area_out) {
   mh::NPParams p;
   p.BK = BK;
   p.BK_inv = 1.0 / BK;
@@ -117,15 +117,16 @@ void dl_master(int64_t n, const double* ax, double Ms, double BK, double beta, d
   std::vector<mh::MasterState> q((size_t)n);
   std::vector<double> prev((size_t)n), sum((size_t)n, 0.0), comp((size_t)n, 0.0);
   for (int64_t i = 0; i < n; ++i) {
-    mh::master_init(q[i], ax[3 * i], ax[3 * i + 1], ax[3 * i + 2]);
-    prev[i] = q[i].ax;
+    mh::master_init(q[i], ax[3 * i], ax[3 * i + 1], ax[3 * i + 2], eh[0], eh[1], eh[2]);
+    prev[i] = q[i].ax * eh[0] + q[i].ay * eh[1] + q[i].az * eh[2];
   }
   const int total = S * n_periods, kept0 = S * n_discard;
   for (int k = 0; k < total; ++k) {
     const double Bext = static_field ? Bmax : Bmax * std::cos(2.0 * mh::kPi * (double)k / (double)S);
     double msum = 0.0;
     for (int64_t i = 0; i < n; ++i) {
-      const double mx = mh::master_step(p, Bext, ax[3 * i], ax[3 * i + 1], ax[3 * i + 2], q[i]);
+      const double mx = mh::master_step(p, Bext, eh[0], eh[1], eh[2], ax[3 * i], ax[3 * i + 1],
+                                        ax[3 * i + 2], q[i]);
       if (k >= kept0) mh::neumaier_add(sum[i], comp[i], Ms * Bext * (mx - prev[i]));
       prev[i] = mx;
       msum += mx;

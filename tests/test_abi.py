@@ -43,3 +43,37 @@ def test_error_strings_without_device():
     h = ctypes.c_void_p()
     rc = L.mh_ctx_create(99, ctypes.byref(h))
     assert rc == -4 and not h.value
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of mh_params, mh_request and mh_result have the header's field
+    offsets and sizes (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    import paper_1407_2737_amd as mh
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"mh_params": mh.Params, "mh_request": mh.Request, "mh_result": mh.Result}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mhkmc.h"',
+             "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    r = subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                        str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = {}
+    for ln in out.splitlines():
+        cname, field, val = ln.split()
+        got[(cname, field)] = int(val)
+    for cname, cls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

@@ -38,7 +38,7 @@ def dl():
                             C.c_int, C.c_uint64, C.c_uint64, C.c_int64, C.c_int, dp]
     L.dl_master.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                             C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
-                            dp, dp]
+                            dp, dp, dp]
     return L
 
 
@@ -143,11 +143,13 @@ def test_update_matches_oracle_step(dl, prob_form, scan):
     assert np.abs(out[:, :3] - m_new).max() < 1e-9
 
 
-@pytest.mark.parametrize("T,prob_form,static", [(300.0, 0, 0), (300.0, 1, 0), (0.0, 0, 0),
-                                                (300.0, 0, 1)])
-def test_master_step_matches_oracle(dl, T, prob_form, static):
+@pytest.mark.parametrize("T,prob_form,static,tilt", [(300.0, 0, 0, 0), (300.0, 1, 0, 0),
+                                                     (0.0, 0, 0, 0), (300.0, 0, 1, 0),
+                                                     (300.0, 0, 0, 1)])
+def test_master_step_matches_oracle(dl, T, prob_form, static, tilt):
     """The mean-magnetisation step (weights over two wells, Sec. II.3) against the
-    oracle's master-equation loop: loop record and area to rounding."""
+    oracle's master-equation loop: loop record and area to rounding; tilt applies the
+    field along (1, 2, -2)/3 instead of x."""
     rng = np.random.default_rng(11 + prob_form + 2 * static)
     n = 60
     axes = rng.normal(size=(n, 3))
@@ -157,12 +159,14 @@ def test_master_step_matches_oracle(dl, T, prob_form, static):
     S, P, D = 100, 3, 1
     p = kmc.Params(Ms=4e5, Keff=1.3e4, d=12e-9, T=T, mu0Hmax=0.03, steps_per_period=S,
                    n_periods=P, n_discard=D, interactions=0, prob_form=prob_form,
-                   dt_override=2e-10 if static else 0.0)
+                   dt_override=2e-10 if static else 0.0,
+                   field_dir=(1.0, 2.0, -2.0) if tilt else (1.0, 0.0, 0.0))
     dv = kmc.derived(p)
     H, M, A = master.mean_loop(axes, p)
     Mg = np.empty((P - D) * S)
     Ag = np.empty(1)
+    eh = kmc.field_unit(p)
     dl.dl_master(n, _p(axes), p.Ms, dv["BK"], dv["beta"], dv["nu0dt"], prob_form,
-                 1 if T > 0 else 0, p.mu0Hmax, S, P, D, static, _p(Mg), _p(Ag))
+                 1 if T > 0 else 0, p.mu0Hmax, S, P, D, static, _p(eh), _p(Mg), _p(Ag))
     assert np.abs(Mg - M.ravel()).max() < 1e-9 * np.abs(M).max()
     assert abs(Ag[0] - A) < 1e-9 * max(abs(A), 1.0), (Ag[0], A)
