@@ -376,9 +376,10 @@ __device__ SWState sw_fall(double hx, double hy, Dir d0) {
 // refined by Newton's method on g from the middle of its interval: at most 50 steps,
 // the first one below 1e-13 being the last, the result wrapped into (-pi, pi] by the
 // IEEE remainder. Products and sums are not fused here, so that the signs of g on the
-// grid, which fix the number of extrema, are rounded as in plain FP64 arithmetic. A point is a minimum where g turns from negative to positive. Near
-// the switching field a saddle and the minimum beside it can share one grid interval
-// and are then not seen: the particle keeps only its stable well.
+// grid, which fix the number of extrema, are rounded as in plain FP64 arithmetic. A
+// point is a minimum where g turns from negative to positive. Near the switching field
+// a saddle and the minimum beside it can share one grid interval and are then not
+// seen: the particle keeps only its stable well.
 // Step v on the sorted points (ascending angle, stable): with four points the moment
 // at theta0 = atan2(d0) falls into the minimum at the end of its arc, one that sits
 // exactly on a maximum into the lower minimum, then the nearer; with fewer points into

@@ -45,8 +45,8 @@ struct SysDesc {
 
 // Operands of the interaction-matrix product (see mh_wm.hip).
 struct WMArgs {
-  const __bf16* whi;
-  const __bf16* wlo;
+  const D4* pos;   // positions in units of d (the W tiles are generated from them)
+  int n;           // particles
   __bf16* mhi;     // M^T hi: Rp x Kp, fragment-major (see mt_offset in mh_wm.hip)
   __bf16* mlo;     // M^T lo
   float* bt;       // B^T: Rp x Mp (reduced dipolar sums)

@@ -36,8 +36,6 @@ int wm_tile_rows();
 int wm_tile_reps();
 int wm_tile_k();
 int wm_ksplit();
-hipError_t launch_wm_build(const D4* pos, int n, __bf16* whi, __bf16* wlo, int Mp, int Kp,
-                           hipStream_t st);
 hipError_t launch_wm_gemm(const WMArgs& g, hipStream_t st);
 hipError_t launch_wm_update(bool scan, const SysDesc* d_sys, int R, int n, const WMArgs& g,
                             const int64_t* kbase, int64_t koff, hipStream_t st);
@@ -156,10 +154,10 @@ struct mh_asm {
   int tile_kind = 0;  // 0: 64 targets per block, 1: 16
   int nsplit = 1;     // source parts per field tile
   DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp, field, dhdip;
-  // interaction-matrix form: W hi/lo (Mp x Kp), M^T hi/lo (Rp x Kp), B^T (Rp x Mp)
-  DevBuf whi, wlo, mhi, mlo, bt;
+  // interaction-matrix form (W generated in the product kernel): M^T hi/lo (Rp x Kp),
+  // B^T partial sums (k splits x Rp x Mp)
+  DevBuf mhi, mlo, bt;
   int Mp = 0, Kp = 0, Rp = 0;
-  bool w_built = false;
   int state_parity = 0;  // the current moments live in buffer state_parity
   int64_t k_origin = 0;    // global step of local step 0 (continuous batching)
   int force_kind = -1, force_bpc = 0;  // autotuner candidates (-1: table or rule)
@@ -320,18 +318,11 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   const bool wm = a->p.precision == MH_BF16X3_WM;
   if (!resident && !wm && (e = a->field.ensure(sizeof(D4) * R * n * a->nsplit))) return e;
   if (wm) {
-    if (!a->w_built) {
+    {
       const int64_t rows = 3 * n;
       const int64_t rq = 8 * wm_tile_rows();  // whole row tiles, a multiple of 8 for the XCD map
       a->Mp = (int)((rows + rq - 1) / rq * rq);
       a->Kp = (int)((rows + wm_tile_k() - 1) / wm_tile_k() * wm_tile_k());
-      const size_t wb = sizeof(__bf16) * (size_t)a->Mp * a->Kp;
-      if ((e = a->whi.ensure(wb)) || (e = a->wlo.ensure(wb))) return e;
-      if (launch_wm_build(a->pos64.as<D4>(), (int)n, a->whi.as<__bf16>(), a->wlo.as<__bf16>(),
-                          a->Mp, a->Kp, a->ctx->stream) != hipSuccess ||
-          hipStreamSynchronize(a->ctx->stream) != hipSuccess)
-        return MH_EDEVICE;
-      a->w_built = true;
     }
     const int rt = wm_tile_reps();
     const int Rp = (int)((R + rt - 1) / rt * rt);
@@ -407,8 +398,8 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
 
 WMArgs wm_args(const mh_asm* a) {
   WMArgs g{};
-  g.whi = a->whi.as<__bf16>();
-  g.wlo = a->wlo.as<__bf16>();
+  g.pos = a->pos64.as<D4>();
+  g.n = (int)a->n;
   g.mhi = a->mhi.as<__bf16>();
   g.mlo = a->mlo.as<__bf16>();
   g.bt = a->bt.as<float>();
@@ -1108,7 +1099,7 @@ int mh_destroy_assembly(mh_asm* a) {
   }
   DevBuf* bufs[] = {&a->pos64, &a->pos32, &a->axes, &a->m64, &a->m32, &a->area, &a->dhdip, &a->recpart,
                     &a->rec, &a->sys_area, &a->stats, &a->diag, &a->tmp, &a->field,
-                    &a->whi, &a->wlo, &a->mhi, &a->mlo, &a->bt};
+                    &a->mhi, &a->mlo, &a->bt};
   for (auto* b : bufs) b->release();
   delete a;
   return MH_OK;
@@ -1508,10 +1499,10 @@ size_t request_bytes(int64_t n, const mh_params& p, int64_t R, int64_t maxR) {
   size_t b = (size_t)R * n * (2 * 32 + 2 * 16 + 16 + 8 + 32) + (size_t)R * rows * (nt + 1) * 8;
   b += (size_t)n * (32 + 16 + 32) + (size_t)maxR * 8 + 4096;
   if (p.precision == MH_BF16X3_WM) {
-    const int64_t rq = 8 * 192;
-    const int64_t Mp = (3 * n + rq - 1) / rq * rq, Kp = (3 * n + 127) / 128 * 128;
-    const int64_t Rp = (R + 255) / 256 * 256;
-    b += (size_t)Mp * Kp * 4 + (size_t)Rp * Kp * 4 + (size_t)2 * Rp * Mp * 4;
+    const int64_t rq = 8 * wm_tile_rows(), kq = wm_tile_k();
+    const int64_t Mp = (3 * n + rq - 1) / rq * rq, Kp = (3 * n + kq - 1) / kq * kq;
+    const int64_t Rp = (R + wm_tile_reps() - 1) / wm_tile_reps() * wm_tile_reps();
+    b += (size_t)Rp * Kp * 4 + (size_t)wm_ksplit() * Rp * Mp * 4;
   }
   return b;
 }

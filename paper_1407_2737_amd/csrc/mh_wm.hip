@@ -13,14 +13,22 @@
 // contiguous), and it writes B^T (replica-major), which the per-particle update then
 // reads contiguously.
 //
-// Tiling: block = 8 waves, tile = 256 replicas x 192 matrix rows over half of k (two k
-// splits whose partial products the update kernel adds in fixed order), k-stage 64.
-// The 192 W rows of a stage (hi and lo) are staged through LDS (double buffered, rows
-// padded to 72 bf16 so that 16-byte fragment reads do not conflict); each wave owns 32
-// replicas x 192 rows (six 32x32 accumulators) and loads its M^T fragments straight
-// from global memory, one stage ahead. The tile size sets the operand traffic from L2
-// per step: W once per replica tile (2x), M^T once per W row tile (3N/192 x). An XCD
-// (block index mod 8) owns whole W row tiles, so each W slab comes from HBM once.
+// W is never stored: each block generates its W tile stage by stage from the
+// positions (FP64 differences, FP32 r^-3 and r^-5 terms, then the hi/lo split), so
+// the only operand streamed from memory is M^T. Generation costs about a quarter of
+// the block's MFMA time in VALU work, which the other wave of each SIMD overlaps.
+//
+// Tiling: block = 8 waves, tile = 256 replicas x 192 matrix rows (64 target particles)
+// over half of k (two k splits whose partial products the update kernel adds in fixed
+// order), k-stage 48 (16 source particles). Thread (tp, c) = (tid / 8, tid % 8)
+// generates the 3x3 blocks of target tp with sources 2c and 2c + 1 of the next stage
+// (rows 3 tp .. 3 tp + 2, columns 6 c .. 6 c + 5) into the other LDS buffer (hi and
+// lo, rows padded to 56 bf16 so that 16-byte fragment reads do not conflict) while
+// the current stage's MFMAs run; the stage's 16 source positions are staged in LDS one
+// stage earlier. Each wave owns 32 replicas x 192 rows (six 32x32 accumulators) and
+// loads its M^T fragments straight from global memory, one stage ahead. An XCD (block
+// index mod 8) works on one (k split, replica tile) pair where the shape allows it, so
+// its blocks share one M^T slab in its L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -29,66 +37,83 @@
 namespace mh {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int WM_BM = 256;  // replicas per block
-constexpr int WM_BN = 192;  // W rows per block
-constexpr int WM_BK = 64;   // k per stage
+constexpr int WM_BN = 192;  // W rows per block (64 target particles)
+constexpr int WM_BK = 48;   // k per stage (16 source particles)
 constexpr int WM_SK = 2;    // k splits (partial products summed by the update)
 constexpr int WM_LD = WM_BK + 8;
+constexpr int WM_SUB = WM_BK / 16;  // MFMA k-steps per stage
 
 __device__ __forceinline__ __bf16 bf16_rn(float x) { return (__bf16)x; }
 
-// M^T is stored fragment-major: for replica tile r/32 and k-stage k/64, the 32 x 64
-// block is laid out as [sub][lane][8] with lane = 32 * (kk / 32) + r % 32,
-// sub = (kk % 32) / 8 (kk = k % 64), so the fragment load of one substep by a wave is
+// M^T is stored fragment-major: for replica tile r/32 and k-stage k/48, the 32 x 48
+// block is laid out as [sub][lane][8] with lane = 32 * (kk / 24) + r % 32,
+// sub = (kk % 24) / 8 (kk = k % 48), so the fragment load of one k-step by a wave is
 // one contiguous 1 KB read.
 __device__ __forceinline__ size_t mt_offset(int r, int k, int Kp) {
   const int rt = r >> 5, rr = r & 31;
-  const int kb = k >> 6, kk = k & 63;
-  const int lane = ((kk >> 5) << 5) + rr;
-  const int sub = (kk & 31) >> 3;
-  return ((((size_t)rt * (Kp >> 6) + kb) * 4 + sub) * 64 + lane) * 8 + (kk & 7);
+  const int kb = k / WM_BK, kk = k - kb * WM_BK;
+  const int lane = (kk / 24) * 32 + rr;
+  const int sub = (kk % 24) >> 3;
+  return ((((size_t)rt * (Kp / WM_BK) + kb) * WM_SUB + sub) * 64 + lane) * 8 + (kk & 7);
 }
 
-// Builds W_hi, W_lo (Mp x Kp bf16, zero padded) from positions in units of d.
-__global__ void k_wm_build(const D4* __restrict__ pos, int n, __bf16* __restrict__ whi,
-                           __bf16* __restrict__ wlo, int Mp, int Kp) {
-  const int a = blockIdx.y;  // row
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= Mp || b >= Kp) return;
-  const int i = a / 3, ca = a - 3 * (a / 3);
-  const int j = b / 3, cb = b - 3 * (b / 3);
-  double w = 0.0;
-  if (i < n && j < n && i != j) {
-    const D4 pi = pos[i], pj = pos[j];
-    const double d[3] = {pj.x - pi.x, pj.y - pi.y, pj.z - pi.z};
-    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    const double inv = 1.0 / sqrt(r2);
-    const double inv3 = inv * inv * inv;
-    w = (3.0 * (d[ca] * inv) * (d[cb] * inv) - (ca == cb ? 1.0 : 0.0)) * inv3;
-  }
-  const __bf16 h = bf16_rn((float)w);
-  const __bf16 l = bf16_rn((float)(w - (double)(float)h));
-  whi[(size_t)a * Kp + b] = h;
-  wlo[(size_t)a * Kp + b] = l;
+// bf16 hi/lo split of two values, packed with a in the low half (the lower address):
+// one pair conversion (round to nearest even) for each part.
+__device__ __forceinline__ void split_pack(float a, float b, uint32_t& hi, uint32_t& lo) {
+  const f32x2 v = {a, b};
+  const bf16x2 h = __builtin_convertvector(v, bf16x2);
+  const bf16x2 l = __builtin_convertvector(v - __builtin_convertvector(h, f32x2), bf16x2);
+  hi = __builtin_bit_cast(uint32_t, h);
+  lo = __builtin_bit_cast(uint32_t, l);
 }
 
+// The 3x3 block T_ij (reduced units) of target position p and source q: q.w = 0 marks
+// a missing source (padding), own = the target itself. Row a of the block in t[3a..].
+__device__ __forceinline__ void pair_block(double px, double py, double pz, bool tgt_ok,
+                                           const D4& q, bool own, float* t) {
+  const bool ok = tgt_ok && q.w != 0.0 && !own;
+  const float dx = (float)(q.x - px), dy = (float)(q.y - py), dz = (float)(q.z - pz);
+  const float r2 = ok ? dx * dx + dy * dy + dz * dz : 1.0f;
+  const float inv = __builtin_amdgcn_rsqf(r2);
+  const float inv2 = inv * inv;
+  const float c3 = ok ? inv * inv2 : 0.0f;
+  const float s5 = 3.0f * c3 * inv2;
+  const float ux = dx * s5, uy = dy * s5, uz = dz * s5;
+  t[0] = dx * ux - c3;
+  t[1] = dx * uy;
+  t[2] = dx * uz;
+  t[3] = dy * ux;
+  t[4] = dy * uy - c3;
+  t[5] = dy * uz;
+  t[6] = dz * ux;
+  t[7] = dz * uy;
+  t[8] = dz * uz - c3;
+}
 
 __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
   __shared__ __attribute__((aligned(16))) __bf16 Ws[2][2][WM_BN][WM_LD];
+  __shared__ D4 Ps[2][16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  // block -> (W row tile, k split, replica tile); XCD-aware when the shape allows it:
-  // an XCD (block index mod 8) owns whole W row tiles, both k splits and both replica
-  // tiles, so each W slab is fetched from HBM once per step into that XCD's L2
+  // block -> (W row tile, k split, replica tile). XCD-aware when the shape allows it:
+  // the C = n_ctiles * WM_SK (k split, replica tile) pairs each get 8 / C XCDs, so the
+  // blocks of an XCD read one M^T slab, from that XCD's L2
   int rt, ks, ct;
   const int nb = g.n_rtiles * g.n_ctiles * WM_SK;
-  if (g.n_ctiles == 2 && (g.n_rtiles & 7) == 0 && nb == (int)gridDim.x) {
+  const int C = g.n_ctiles * WM_SK;
+  if ((C == 1 || C == 2 || C == 4 || C == 8) && nb == (int)gridDim.x &&
+      g.n_rtiles % (8 / C) == 0) {
+    const int X = 8 / C;  // XCDs per pair
     const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-    rt = xcd * (g.n_rtiles >> 3) + (slot >> 2);
-    ks = (slot >> 1) & 1;
-    ct = slot & 1;
+    const int pair = xcd / X;
+    ks = pair % WM_SK;
+    ct = pair / WM_SK;
+    rt = (xcd % X) * (g.n_rtiles / X) + slot;
   } else {
     ct = blockIdx.x % g.n_ctiles;
     ks = (blockIdx.x / g.n_ctiles) % WM_SK;
@@ -97,103 +122,142 @@ __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
   const int wrow0 = rt * WM_BN;           // first W row (output column) of the block
   const int rep0 = ct * WM_BM + w * 32;   // the wave's 32 replicas (output rows)
   const int kbeg = ks * (g.Kp / WM_SK);
-  // M^T fragments of the wave's 32-replica tile (fragment-major layout, see mt_offset):
-  // k-stage kb, substep s at ((tile * nkb + kb) * 4 + s) * 64 * 8 + lane * 8
-  const int nkb = g.Kp >> 6;
-  const size_t aoff = (size_t)(rep0 >> 5) * nkb * 4 * 64 * 8 + (size_t)lane * 8;
+  const int jbeg = kbeg / 3;              // first source particle of the k split
+  const int nst = g.Kp / WM_SK / WM_BK;
+  // M^T fragments of the wave's 32-replica tile (fragment-major layout, see mt_offset)
+  const int nkb = g.Kp / WM_BK;
+  const size_t aoff = (size_t)(rep0 >> 5) * nkb * WM_SUB * 512 + (size_t)lane * 8;
   const __bf16* ah = g.mhi + aoff;
   const __bf16* al = g.mlo + aoff;
-  // W stage loads: 192 rows x 8 chunks of 8 bf16, hi and lo = 3072 chunks, 6 per thread
-  // (rows tid/8 + 64 q for q = 0, 1, 2 of hi, then of lo), held in named registers (a
-  // register array here would be moved to LDS)
-  const int wr = tid >> 3, wk = (tid & 7) * 8;
-  const __bf16* wsrc_h = g.whi + (size_t)(wrow0 + wr) * g.Kp + wk;
-  const __bf16* wsrc_l = g.wlo + (size_t)(wrow0 + wr) * g.Kp + wk;
-  const size_t wstep = (size_t)64 * g.Kp;  // 64 rows further for the next q
-  uint4 w0, w1, w2, w3, w4, w5;
-#define MH_LOAD_W(k0)                                                             \
+  bf16x8 an[2][WM_SUB];  // next stage M^T fragments [hi/lo][k-step]
+#define MH_LOAD_A(st_)                                                           \
   do {                                                                           \
-    w0 = *reinterpret_cast<const uint4*>(wsrc_h + (k0));                         \
-    w1 = *reinterpret_cast<const uint4*>(wsrc_h + wstep + (k0));                 \
-    w2 = *reinterpret_cast<const uint4*>(wsrc_h + 2 * wstep + (k0));             \
-    w3 = *reinterpret_cast<const uint4*>(wsrc_l + (k0));                         \
-    w4 = *reinterpret_cast<const uint4*>(wsrc_l + wstep + (k0));                 \
-    w5 = *reinterpret_cast<const uint4*>(wsrc_l + 2 * wstep + (k0));             \
-  } while (0)
-#define MH_STORE_W(buf)                                                          \
-  do {                                                                           \
-    *reinterpret_cast<uint4*>(&Ws[buf][0][wr][wk]) = w0;                         \
-    *reinterpret_cast<uint4*>(&Ws[buf][0][wr + 64][wk]) = w1;                    \
-    *reinterpret_cast<uint4*>(&Ws[buf][0][wr + 128][wk]) = w2;                   \
-    *reinterpret_cast<uint4*>(&Ws[buf][1][wr][wk]) = w3;                         \
-    *reinterpret_cast<uint4*>(&Ws[buf][1][wr + 64][wk]) = w4;                    \
-    *reinterpret_cast<uint4*>(&Ws[buf][1][wr + 128][wk]) = w5;                   \
-  } while (0)
-  bf16x8 an[2][4];  // next stage M^T fragments [hi/lo][sub]
-#define MH_LOAD_A(k0)                                                            \
-  do {                                                                           \
-    _Pragma("unroll") for (int s = 0; s < 4; ++s) {                              \
-      an[0][s] = *reinterpret_cast<const bf16x8*>(ah + ((k0) >> 6) * 2048 + s * 512); \
-      an[1][s] = *reinterpret_cast<const bf16x8*>(al + ((k0) >> 6) * 2048 + s * 512); \
+    const size_t o_ = (size_t)(kbeg / WM_BK + (st_)) * (WM_SUB * 512);           \
+    _Pragma("unroll") for (int s = 0; s < WM_SUB; ++s) {                         \
+      an[0][s] = *reinterpret_cast<const bf16x8*>(ah + o_ + s * 512);            \
+      an[1][s] = *reinterpret_cast<const bf16x8*>(al + o_ + s * 512);            \
     }                                                                            \
   } while (0)
+  // generation: target tp of the block, sources 2c, 2c+1 of a stage
+  const int tp = tid >> 3, c = tid & 7;
+  const int it = rt * 64 + tp;
+  const bool tgt_ok = it < g.n;
+  const D4 pt = g.pos[tgt_ok ? it : 0];
+  // source positions of stage st_ for threads 0..15: q.w = 1 marks a real particle
+  auto src_of = [&](int st_) -> D4 {
+    const int j = jbeg + 16 * st_ + tid;
+    D4 q = {0.0, 0.0, 0.0, 0.0};
+    if (st_ < nst && j < g.n) {
+      q = g.pos[j];
+      q.w = 1.0;
+    }
+    return q;
+  };
+  uint32_t gh[9], gl[9];  // generated rows 3tp..3tp+2 x columns 6c..6c+5, hi and lo
+  auto generate = [&](int st_) {
+    const int pb = st_ & 1;
+    const int j0 = jbeg + 16 * st_ + 2 * c;
+    float t0[9], t1[9];
+    pair_block(pt.x, pt.y, pt.z, tgt_ok, Ps[pb][2 * c], j0 == it, t0);
+    pair_block(pt.x, pt.y, pt.z, tgt_ok, Ps[pb][2 * c + 1], j0 + 1 == it, t1);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      split_pack(t0[3 * a], t0[3 * a + 1], gh[3 * a], gl[3 * a]);
+      split_pack(t0[3 * a + 2], t1[3 * a], gh[3 * a + 1], gl[3 * a + 1]);
+      split_pack(t1[3 * a + 1], t1[3 * a + 2], gh[3 * a + 2], gl[3 * a + 2]);
+    }
+  };
+  auto store_w = [&](int buf) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      uint32_t* dh = reinterpret_cast<uint32_t*>(&Ws[buf][0][3 * tp + a][6 * c]);
+      uint32_t* dl = reinterpret_cast<uint32_t*>(&Ws[buf][1][3 * tp + a][6 * c]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        dh[q] = gh[3 * a + q];
+        dl[q] = gl[3 * a + q];
+      }
+    }
+  };
+
   f32x16 acc[6];
 #pragma unroll
   for (int u = 0; u < 6; ++u)
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[u][e] = 0.f;
 
-  const int nst = g.Kp / WM_SK / WM_BK;
-  MH_LOAD_W(kbeg);
-  MH_LOAD_A(kbeg);
-  MH_STORE_W(0);
+  // prologue: source positions of stages 0 and 1, W of stage 0, M^T of stage 0
+  MH_LOAD_A(0);
+  if (tid < 16) {
+    Ps[0][tid] = src_of(0);
+    Ps[1][tid] = src_of(1);
+  }
+  __syncthreads();
+  generate(0);
+  store_w(0);
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
-    bf16x8 ac[2][4];
+    bf16x8 ac[2][WM_SUB];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) ac[h][s] = an[h][s];
-    if (st + 1 < nst) {
-      MH_LOAD_W(kbeg + (st + 1) * WM_BK);
-      MH_LOAD_A(kbeg + (st + 1) * WM_BK);
+      for (int s = 0; s < WM_SUB; ++s) ac[h][s] = an[h][s];
+    const bool more = st + 1 < nst;
+    D4 pnext = {0.0, 0.0, 0.0, 0.0};
+    if (more) {
+      MH_LOAD_A(st + 1);
+      if (tid < 16) pnext = src_of(st + 2);
     }
-    // keep the next stage's loads in flight across the MFMAs: no memory operation may
-    // move over this point, and the LDS stores of the next stage stay after them
+    // keep the next stage's loads in flight across the MFMAs
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
+    auto mfmas = [&]() {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = (lane >> 5) * 32 + s * 8;
-      bf16x8 bh[6], bl[6];
+      for (int s = 0; s < WM_SUB; ++s) {
+        const int kk = (lane >> 5) * 24 + s * 8;
+        bf16x8 bh[6], bl[6];
 #pragma unroll
-      for (int u = 0; u < 6; ++u) {
-        bh[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][0][u * 32 + (lane & 31)][kk]);
-        bl[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][1][u * 32 + (lane & 31)][kk]);
+        for (int u = 0; u < 6; ++u) {
+          bh[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][0][u * 32 + (lane & 31)][kk]);
+          bl[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][1][u * 32 + (lane & 31)][kk]);
+        }
+        // the three split products sweep the six accumulators in turn, so consecutive
+        // MFMAs never depend on each other
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bh[u], acc[u], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[1][s], bh[u], acc[u], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bl[u], acc[u], 0, 0, 0);
       }
-      // the three split products sweep the six accumulators in turn, so consecutive
-      // MFMAs never depend on each other
-#pragma unroll
-      for (int u = 0; u < 6; ++u)
-        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bh[u], acc[u], 0, 0, 0);
-#pragma unroll
-      for (int u = 0; u < 6; ++u)
-        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[1][s], bh[u], acc[u], 0, 0, 0);
-#pragma unroll
-      for (int u = 0; u < 6; ++u)
-        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bl[u], acc[u], 0, 0, 0);
+    };
+    // W of the next stage from the staged positions. Waves w and w + 4 share a SIMD:
+    // the first half generates before its MFMAs and the second after them, so that on
+    // each SIMD one wave's VALU work runs beside the other's MFMAs (wave-uniform branch)
+    if (w < 4) {
+      if (more) generate(st + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfmas();
+    } else {
+      mfmas();
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) generate(st + 1);
     }
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    if (st + 1 < nst) {
-      MH_STORE_W(cur ^ 1);
+    if (more) {
+      // every wave has finished reading Ws[cur ^ 1] (stage st - 1) and Ps[st & 1]
+      // (generated into W of stage st) before the previous barrier
+      store_w(cur ^ 1);
+      if (tid < 16) Ps[st & 1][tid] = pnext;
       __syncthreads();
     }
   }
 #undef MH_LOAD_A
-#undef MH_LOAD_W
-#undef MH_STORE_W
   // partial B^T of k split ks: lane holds column wrow0 + u*32 + lane%32 of rows
   // rep0 + 8*(e/4) + 4*(lane/32) + e%4
   float* bt = g.bt + (size_t)ks * g.Rp * g.Mp;
@@ -280,13 +344,6 @@ int wm_tile_rows() { return WM_BN; }
 int wm_tile_reps() { return WM_BM; }
 int wm_tile_k() { return WM_BK * WM_SK; }
 int wm_ksplit() { return WM_SK; }
-
-hipError_t launch_wm_build(const D4* pos, int n, __bf16* whi, __bf16* wlo, int Mp, int Kp,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_wm_build, dim3((Kp + 255) / 256, Mp), dim3(256), 0, st, pos, n, whi, wlo,
-                     Mp, Kp);
-  return hipGetLastError();
-}
 
 hipError_t launch_wm_gemm(const WMArgs& g, hipStream_t st) {
   hipLaunchKernelGGL(k_wm_gemm, dim3(g.n_rtiles * g.n_ctiles * WM_SK), dim3(512), 0, st, g);
