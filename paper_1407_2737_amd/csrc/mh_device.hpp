@@ -599,8 +599,12 @@ __device__ __forceinline__ Plane working_plane(const NPParams& p, double Bx, dou
 
 // Eq. 5 for both directions between the wells c and o (a = barrier / k_B T): P_co
 // to leave c for o and P_oc the reverse. sigma = 1 / (1 + e^(a_c - a_o)) is formed as
-// e^-a_c / (e^-a_c + e^-a_o); with both terms underflowed the bracket
-// -expm1(-nu0 dt * 0) is 0 and so are both. The single-rate form is -expm1(-nu0 dt e^-a).
+// e^-a_c / (e^-a_c + e^-a_o). Below kSumMin the reciprocal of that sum would overflow
+// (a subnormal sum); both probabilities are then at most nu0 dt kSumMin, below any
+// nonzero draw (2^-53), and are returned as 0. The single-rate form is
+// -expm1(-nu0 dt e^-a).
+constexpr double kSumMin = 0x1p-1000;
+
 __device__ __forceinline__ void transition_pair(const NPParams& p, double a_c, double a_o,
                                                 double& P_co, double& P_oc) {
   const double xc = exp(-a_c), xo = exp(-a_o);
@@ -610,7 +614,7 @@ __device__ __forceinline__ void transition_pair(const NPParams& p, double a_c, d
     return;
   }
   const double sum = xc + xo;
-  if (!(sum > 0.0)) {
+  if (!(sum >= kSumMin)) {
     P_co = P_oc = 0.0;
     return;
   }
@@ -657,10 +661,10 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
     if (p.prob_form == 1) {
       P = -expm1(-p.nu0dt * exp(-a_c));
     } else {
-      // sigma = 1 / (1 + e^(a_c - a_o)) = e^-a_c / (e^-a_c + e^-a_o); with both terms
-      // underflowed the bracket -expm1(-nu0 dt * 0) is 0 and so is P
+      // sigma = 1 / (1 + e^(a_c - a_o)) = e^-a_c / (e^-a_c + e^-a_o); below kSumMin
+      // P is at most nu0 dt kSumMin and is taken as 0 (see transition_pair)
       const double xc = exp(-a_c), xo = exp(-a_o), sum = xc + xo;
-      P = sum > 0.0 ? (xc * rcp64(sum)) * (-expm1(-p.nu0dt * sum)) : 0.0;
+      P = sum >= kSumMin ? (xc * rcp64(sum)) * (-expm1(-p.nu0dt * sum)) : 0.0;
     }
     const double u = philox_uniform(seed, stream, i, k);
     out.P = P;

@@ -146,7 +146,9 @@ __global__ __launch_bounds__(256) void k_resident(const SysDesc* __restrict__ sy
       T bx = 0, by = 0, bz = 0;
       if (i < n) {
         const P4 pi = pos[i];
-        for (int j = sub; j < n; j += P) dip_pair<T>((T)pi.x, (T)pi.y, (T)pi.z, pos[j], mc[j], bx, by, bz);
+        if (s.Bscale != 0.0)  // interactions on (uniform over the block)
+          for (int j = sub; j < n; j += P)
+            dip_pair<T>((T)pi.x, (T)pi.y, (T)pi.z, pos[j], mc[j], bx, by, bz);
       }
       for (int off = P >> 1; off > 0; off >>= 1) {
         bx += __shfl_xor(bx, off, 64);

@@ -358,7 +358,9 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.recpart = a->recpart.as<double>() + r * rows * a->ntiles;
   s.rec = a->rec.as<double>() + r * rows;
   s.field = a->resident ? nullptr : a->field.as<D4>() + r * n * a->nsplit;
-  s.nsplit = a->nsplit;
+  // without interactions no dipolar sum is formed: no field tiles, and the update
+  // reads no partial sums (its dipolar part is exactly zero)
+  s.nsplit = a->p.interactions ? a->nsplit : 0;
   s.sys_area = a->sys_area.as<double>() + r;
   s.dhdip = a->dhdip.as<double>() + r * n;
   s.diag = nullptr;

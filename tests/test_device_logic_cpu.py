@@ -170,3 +170,54 @@ def test_master_step_matches_oracle(dl, T, prob_form, static, tilt):
                  1 if T > 0 else 0, p.mu0Hmax, S, P, D, static, _p(eh), _p(Mg), _p(Ag))
     assert np.abs(Mg - M.ravel()).max() < 1e-9 * np.abs(M).max()
     assert abs(Ag[0] - A) < 1e-9 * max(abs(A), 1.0), (Ag[0], A)
+
+
+def test_eq5_where_both_rates_underflow(dl):
+    """Fig. 1(d) at T = 5 K (beta = 13107): barriers of about 0.055 K V put both
+    e^-a terms of Eq. 5 near 1e-310, where a reciprocal of their sum overflows. The
+    step must give P (within 1e-12 of the oracle's, which is below 1e-290 there) and
+    the oracle's jump decisions, and the mean loop must stay finite and equal. At this
+    beta an energy rounding of a few ulps moves a = beta * barrier by ~beta * 4e-16,
+    so P is held to 5e-16 beta instead of 1e-12, and a decision may differ only
+    where u lies that close to P."""
+    rng = np.random.default_rng(41)
+    n = 6000
+    p = kmc.Params(Ms=1e6, Keff=1e6, d=12e-9, T=5.0, mu0Hmax=2.5, interactions=0,
+                   steps_per_period=200, n_periods=2, n_discard=1)
+    dv = kmc.derived(p)
+    axes = rng.normal(size=(n, 3))
+    axes /= np.linalg.norm(axes, axis=1, keepdims=True)
+    m = axes.copy()
+    # fields just inside the switching field of each particle, opposite to its moment,
+    # so the metastable barrier sweeps through 0..0.2 K V
+    ph = rng.uniform(0.05, np.pi / 2 - 0.05, n)
+    hsw = (np.cos(ph) ** (2 / 3) + np.sin(ph) ** (2 / 3)) ** -1.5
+    h = hsw * (1 - rng.uniform(0.0, 0.6, n) ** 2)
+    perp = np.cross(axes, rng.normal(size=(n, 3)))
+    perp /= np.linalg.norm(perp, axis=1, keepdims=True)
+    B = dv["BK"] * h[:, None] * (-np.cos(ph)[:, None] * axes + np.sin(ph)[:, None] * perp)
+    m_new, info = kmc.step(np.zeros((n, 3)), axes, m, 77, p, 9, 0, B_override=B)
+    a_c = dv["beta"] * (info.e3 - info.e_c)
+    a_o = dv["beta"] * (info.e3 - info.e_o)
+    band = info.two & (np.exp(-a_c) + np.exp(-a_o) < 2.2e-308) & (np.exp(-a_c) > 0)
+    assert band.sum() > 10, band.sum()
+    out = np.empty((n, 6))
+    dl.dl_update(n, _p(B), _p(axes), _p(m), dv["BK"], dv["beta"], dv["nu0dt"], 0, 1, 9, 0, 77,
+                 0, _p(out))
+    assert np.all(np.isfinite(out))
+    tol = 5e-16 * dv["beta"]
+    assert np.abs(out[:, 3] - info.P).max() < tol
+    dif = (out[:, 4] == 1.0) != info.jump
+    assert np.all((np.abs(info.u - info.P) < tol)[dif])
+    # the mean loop through the same regime
+    n2 = 60
+    ax2 = axes[:n2].copy()
+    H, M, A = master.mean_loop(ax2, p)
+    Mg = np.empty(p.steps_per_period)
+    Ag = np.empty(1)
+    eh = kmc.field_unit(p)
+    dl.dl_master(n2, _p(ax2), p.Ms, dv["BK"], dv["beta"], dv["nu0dt"], 0, 1, p.mu0Hmax,
+                 p.steps_per_period, 2, 1, 0, _p(eh), _p(Mg), _p(Ag))
+    assert np.all(np.isfinite(Mg)) and np.isfinite(Ag[0])
+    assert np.abs(Mg - M.ravel()).max() < 1e-9 * np.abs(M).max()
+    assert abs(Ag[0] - A) < 1e-9 * abs(A)
