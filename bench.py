@@ -65,7 +65,8 @@ def main():
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="config 3: built-in launch-shape rule")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4plain", "c5", "c5wm", "master", "sweep", "methods"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4plain", "c5", "c5wm", "master", "sweep",
+                             "methods", "figs"])
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--max-replicas", type=int, default=64)
     ap.add_argument("--assemblies", type=int, default=256)
@@ -90,6 +91,8 @@ def main():
         return bench_sweep(args, mh, W)
     if args.workload == "methods":
         return bench_methods(args, mh, W)
+    if args.workload == "figs":
+        return bench_figs(args, mh, W)
     if args.workload in ("c5", "c5wm"):
         return bench_c5(args, mh, W)
     if args.workload != "c2":
@@ -318,6 +321,138 @@ def bench_sweep(args, mh, W):
             "config": {"workload": "concentration sweep: 3000 NPs, lattice + maximal disorder, "
                                    "T=0, Ms=1e6, K=1.3e4, 40 mT, 8 axis sets, phi 0.01-30 %",
                        "A_over_K_vs_dimensionless_concentration": curve}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_figs(args, mh, W):
+    """Parameter sweeps of Sec. III.2-4 as one batch of assemblies, giving the curves of
+    Fig. 4(a) (area against phi for d -> infinity at T = 0, d = 20 nm, d = 9 nm and
+    K = T = 0), Fig. 6(a) (d = 20 nm at 40 mT, 1 T and 7 mT), Fig. 7 (A/K against
+    mu0 Ms^2 phi / K for an anisotropy and a magnetisation series at T = 0, with
+    mu0 Hmax / K fixed in the anisotropy series) and Fig. 10 (9 nm particles, lysosomes
+    of 10 to 3000). Defaults are the paper's (Ms = 1e6 A/m, K = 13000 J/m^3, T = 300 K,
+    40 mT, 100 kHz, nu0 = 1e10 Hz); 3000 particles on a maximally disordered cubic
+    lattice, 8 random 3-D axis sets per point as replicas (the paper's averaging over
+    axis orientations), 2 periods of 2000 steps with the first discarded. The phi
+    points are those of Fig. 5 (0.01-30 %); points that the lattice cannot place (10
+    and 100 particles at 30 %) are skipped. The dilute end of each finite-size series
+    is set against the deterministic loop of the same particles without interactions
+    (mean-magnetisation kernel, same axis sets and amplitudes), and the T = 0 series
+    against the Stoner-Wohlfarth value 1.977 (at mu0 Ms^2 phi / K <= 0.02 interactions
+    are negligible)."""
+    import numpy as np
+    mu0 = 4e-7 * np.pi
+    phis = [1e-4, 5e-4, 1e-3, 3e-3, 6e-3, 1e-2, 2e-2, 3e-2, 0.1, 0.3]
+    sets = 8
+    base = dict(Ms=1e6, Keff=1.3e4, T=300.0, f=1e5, mu0Hmax=0.04, n_periods=2, n_discard=1)
+    # (name, figures, particles, d, overrides, per-replica amplitudes or None)
+    series = [("d_inf_T0", "4a,7", 3000, 20e-9, dict(T=0.0), None),
+              ("d20nm", "4a,6a", 3000, 20e-9, {}, (0.04, 1.0, 0.007)),
+              ("d9nm", "4a,10", 3000, 9e-9, {}, None),
+              ("K0_T0", "4a", 3000, 20e-9, dict(Keff=0.0, T=0.0), None)]
+    for K in (6e3, 1e5, 1e6):
+        series.append((f"T0_K{K:g}", "7", 3000, 20e-9,
+                       dict(T=0.0, Keff=K, mu0Hmax=0.04 * K / 1.3e4), None))
+    for Ms in (7e5, 1.7e6):
+        series.append((f"T0_Ms{Ms:g}", "7", 3000, 20e-9, dict(T=0.0, Ms=Ms), None))
+    for N in (10, 100, 1000):
+        series.append((f"d9nm_N{N}", "10", N, 9e-9, {}, None))
+    ctx = mh.Context(0)
+    asms, meta, Rs, skipped = [], [], [], []
+    q = 0
+    for si, (name, figs, n, d, over, amps) in enumerate(series):
+        kw = dict(base, d=d, **over)
+        for phi in phis:
+            q += 1
+            radius = 0.5 * d * (n / phi) ** (1.0 / 3.0)
+            try:
+                pos = W.place_lattice_disorder(n, radius, d, 9000 + q)
+            except RuntimeError:
+                skipped.append({"series": name, "phi": phi})
+                continue
+            axes = np.concatenate([W.axes_random_3d(n, 9500 + 10 * si + k) for k in range(sets)])
+            a = mh.Assembly(ctx, pos, axes, mh.Params.make(mh.FP32_FIELD, **kw), n_axes_sets=sets)
+            R = sets
+            if amps:
+                a.set_replica_fields(list(amps))
+                R = sets * len(amps)
+            asms.append(a)
+            Rs.append(R)
+            meta.append((si, phi, n, kw))
+    steps_per_run = 2 * 2000
+    seeds = [12000 + i for i in range(len(asms))]
+
+    def one_run():
+        mh.run_batch(asms, Rs, seeds)
+        for a in asms:
+            a.sync()
+
+    for _ in range(args.warmup):
+        one_run()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_run()
+    wall = time.perf_counter() - t0
+    npsteps = sum(m[2] * R for m, R in zip(meta, Rs)) * steps_per_run * args.steps
+    # curves
+    out = {}
+    for (si, phi, n, kw), a, R in zip(meta, asms, Rs):
+        name, figs, _, d, over, amps = series[si]
+        ra = a.replica_areas()
+        groups = [(f"{h * 1e3:g} mT", ra[k::len(amps)]) for k, h in enumerate(amps)] if amps \
+            else [("", ra)]
+        for label, vals in groups:
+            key = name + (f"_{label.replace(' ', '')}" if label else "")
+            A = float(vals.mean())
+            se = float(vals.std(ddof=1) / np.sqrt(len(vals)))
+            pt = {"phi": phi, "area_Jm3": A, "se": se, "sar_W_per_g": A * kw["f"] / 5200.0 / 1e3}
+            if kw["Keff"] > 0:
+                pt["mu0_Ms2_phi_over_K"] = mu0 * kw["Ms"] ** 2 * phi / kw["Keff"]
+                pt["A_over_K"] = A / kw["Keff"]
+            out.setdefault(key, {"figures": figs, "n": n, "d_nm": d * 1e9, "points": []})
+            out[key]["points"].append(pt)
+    # dilute-limit checks
+    checks = {}
+    for si, (name, figs, n, d, over, amps) in enumerate(series):
+        kw = dict(base, d=d, **over)
+        first = next(((m, a) for m, a in zip(meta, asms) if m[0] == si), None)
+        if first is None:
+            continue
+        (_, phi0, _, _), a0 = first
+        if kw["T"] > 0 and kw["Keff"] > 0:
+            pos = W.place_lattice_disorder(n, 0.5 * d * (n / phi0) ** (1 / 3), d, 1)
+            axes = np.concatenate([W.axes_random_3d(n, 9500 + 10 * si + k) for k in range(sets)])
+            b = mh.Assembly(ctx, pos, axes, mh.Params.make(mh.FP64, **dict(kw, interactions=0)),
+                            n_axes_sets=sets)
+            R = sets
+            if amps:
+                b.set_replica_fields(list(amps))
+                R = sets * len(amps)
+            b.run_mean_loop(R)
+            b.sync()
+            det = b.replica_areas()
+            b.close()
+            ra = a0.replica_areas()
+            for k, h in enumerate(amps or (kw["mu0Hmax"],)):
+                sl = slice(k, None, len(amps)) if amps else slice(None)
+                kmc_v, det_v = ra[sl], det[sl]
+                se = float(kmc_v.std(ddof=1) / np.sqrt(len(kmc_v)))
+                checks[f"{name}_{h * 1e3:g}mT"] = {
+                    "phi": phi0, "kmc_area": float(kmc_v.mean()), "se": se,
+                    "no_interaction_area": float(det_v.mean()),
+                    "z": float((kmc_v.mean() - det_v.mean()) / max(se, 1e-12))}
+        elif kw["T"] == 0 and kw["Keff"] > 0:
+            ra = a0.replica_areas()
+            checks[name] = {"phi": phi0, "A_over_K": float(ra.mean() / kw["Keff"]),
+                            "stoner_wohlfarth": 1.977,
+                            "mu0_Ms2_phi_over_K": mu0 * kw["Ms"] ** 2 * phi0 / kw["Keff"]}
+    line = {"metric": "NP·steps/s (dipolar+kMC)", "value": npsteps / wall, "unit": "NP·steps/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 field / f64 barrier", "data": "synthetic",
+            "config": {"workload": f"parameter sweeps of Figs. 4a/6a/7/10: {len(asms)} assemblies "
+                                   f"in one batch, {sum(Rs)} replicas, 2 periods x 2000 steps",
+                       "curves": out, "dilute_limit_checks": checks, "skipped": skipped}}
     print(json.dumps(line), flush=True)
 
 
