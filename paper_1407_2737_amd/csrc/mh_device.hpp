@@ -218,6 +218,167 @@ struct SWState {
 
 // Step iv-v: stationary points for (hx, hy) with hy >= 0, and the basin of the moment at
 // angle theta0, given as its direction d0 = (sin theta0, cos theta0).
+// ---- general case of steps iv-v, in pieces ----
+// With the field reflected into hx > 0 (theta -> pi - theta flips the cosine): the
+// global minimum r1; t* (the zero of g' between the saddle and the metastable minimum)
+// with the two starts around it; the saddle r2a and the metastable minimum r2b; and the
+// energies and basin of step v. sw_fall runs them in order; the update kernel can run
+// the roots on separate waves, with the same arithmetic.
+struct SWArgs {
+  bool refl;       // hx < 0: reflected
+  double ax, hy;   // |hx|, hy
+  float axf, hyf;
+};
+
+__device__ __forceinline__ SWArgs sw_args(double hx, double hy) {
+  SWArgs a;
+  a.refl = hx < 0.0;
+  a.ax = fabs(hx);
+  a.hy = hy;
+  a.axf = (float)a.ax;
+  a.hyf = (float)hy;
+  return a;
+}
+
+// global minimum r1 in (0, pi/2), from the FP32 start r1 = hy / (1 + hx)
+__device__ __forceinline__ Dir sw_min1(const SWArgs& a) {
+  const float kHalfPiF = (float)kHalfPi;
+  const Dir east{0.0, 1.0}, north{1.0, 0.0};
+  float fs, fc;
+  seed_root<false>(0.f, kHalfPiF, true, a.axf, a.hyf, a.hyf * __builtin_amdgcn_rcpf(1.f + a.axf),
+                   fs, fc);
+  return polish_root<false>(east, north, true, a.ax, a.hy, unit(fs, fc));
+}
+
+struct SWT {
+  bool two;   // two minima
+  Dir dt;     // direction of t*
+  float ts;   // t*
+  float q;    // half-distance of the two starts from t*
+};
+
+// Inside the astroid: a direction between the saddle maximum and the metastable minimum
+// in (pi/2, pi) (the FP32 zero t* of g' from the start 3 pi / 4 + (hx - hy) / (2 sqrt 2),
+// kept when g < 0 there in double precision, else polished), and the starts
+// t* -+ sqrt(-2 g / g''), the zeros of g's quadratic expansion about its minimum t*
+// (exact as the pair merges at the astroid).
+__device__ __forceinline__ SWT sw_tstar(const SWArgs& a) {
+  const float kPiF = (float)kPi, kHalfPiF = (float)kHalfPi;
+  const Dir north{1.0, 0.0}, west{0.0, -1.0};
+  SWT t;
+  t.two = false;
+  t.dt = Dir{0.0, 0.0};
+  t.ts = 0.f;
+  t.q = 0.f;
+  if (!astroid_bistable(a.ax, a.hy)) return t;
+  const double ax = a.ax, hy = a.hy;
+  const float axf = a.axf, hyf = a.hyf;
+  float fs, fc;
+  float ts = seed_root<true>(kHalfPiF, kPiF, true, axf, hyf,
+                             0.75f * kPiF + 0.35355339f * (axf - hyf), fs, fc);
+  Dir dt = unit(fs, fc);
+  if (!(dt.s > 0.0 && dt.c < 0.0 && ts > kHalfPiF && ts < kPiF)) {
+    ts = 0.75f * kPiF;
+    dt = unit(1.0, -1.0);
+  }
+  double gt = dt.s * dt.c + ax * dt.s - hy * dt.c;
+  if (!(gt < 0.0)) {
+    dt = polish_root<true>(north, west, true, ax, hy, dt);
+    gt = dt.s * dt.c + ax * dt.s - hy * dt.c;
+    ts = atan2f((float)dt.s, (float)dt.c);
+  }
+  t.dt = dt;
+  t.ts = ts;
+  if (gt < 0.0) {
+    t.two = true;
+    float g2;
+    const float st = (float)dt.s, ct = (float)dt.c;
+    const float g0 = sw_fn<false>(st, ct, axf, hyf, g2);
+    sw_fn<true>(st, ct, axf, hyf, g2);
+    t.q = sqrtf(-2.f * g0 * __builtin_amdgcn_rcpf(g2));
+  }
+  return t;
+}
+
+// saddle maximum r2a in (pi/2, t*)
+__device__ __forceinline__ Dir sw_saddle(const SWArgs& a, const SWT& t) {
+  const float kHalfPiF = (float)kHalfPi;
+  const Dir north{1.0, 0.0};
+  float fs, fc;
+  seed_root<false>(kHalfPiF, t.ts, false, a.axf, a.hyf, t.ts - t.q, fs, fc);
+  return polish_root<false>(north, t.dt, false, a.ax, a.hy, unit(fs, fc));
+}
+
+// metastable minimum r2b in (t*, pi)
+__device__ __forceinline__ Dir sw_meta(const SWArgs& a, const SWT& t) {
+  const float kPiF = (float)kPi;
+  const Dir west{0.0, -1.0};
+  float fs, fc;
+  seed_root<false>(t.ts, kPiF, true, a.axf, a.hyf, t.ts + t.q, fs, fc);
+  return polish_root<false>(t.dt, west, true, a.ax, a.hy, unit(fs, fc));
+}
+
+// Step v from the roots (reflected frame): energies, the basin of theta0 (direction d0),
+// and the state in the unreflected frame.
+__device__ __forceinline__ SWState sw_finish(const SWArgs& a, Dir d0, Dir d1, bool two, Dir d2a,
+                                             Dir d2b) {
+  SWState r;
+  const bool refl = a.refl;
+  const double ax = a.ax, hy = a.hy;
+  const double e1 = sw_energy(d1.s, d1.c, ax, hy);
+  const Dir u1{d1.s, refl ? -d1.c : d1.c};  // unreflected directions
+  if (!two) {
+    r.two = false;
+    r.e_c = r.e_o = e1;
+    r.e3 = 0.0;
+    r.s_c = r.s_o = u1.s;
+    r.c_c = r.c_o = u1.c;
+    return r;
+  }
+  const double e2a = sw_energy(d2a.s, d2a.c, ax, hy);
+  const double e2b = sw_energy(d2b.s, d2b.c, ax, hy);
+  const Dir u2{d2b.s, refl ? -d2b.c : d2b.c};
+  // Basin of theta0. In the reflected frame (angle y, sine sr, cosine cr) the circle
+  // reads r1 (min) < r2a (max) < r2b (min) < r3 (max) < r1 + 2 pi with r1 in (0, pi/2),
+  // r2a and r2b in (pi/2, pi) and r3 in (pi, 3 pi/2):
+  //   cr >= 0           y in [-pi/2, pi/2], before r2a: minimum r1;
+  //   cr < 0, sr >= 0   y in (pi/2, pi]: before r2a iff sin(r2a - y) > 0;
+  //   cr < 0, sr < 0    y in (pi, 3 pi/2): before r3 iff g(y) > 0, as r3 is the only
+  //                     zero of g there and g(pi) = hy > 0 > -ax = g(3 pi/2).
+  // A zero sine or g puts the moment on a maximum (basin 0).
+  const Dir y{d0.s, refl ? -d0.c : d0.c};
+  int basin;  // 1: r1, 2: r2b, 0: on a maximum
+  if (y.c >= 0.0) {
+    basin = 1;
+  } else if (y.s >= 0.0) {
+    const double x = cross(y, d2a);
+    basin = x > 0.0 ? 1 : (x < 0.0 ? 2 : 0);
+  } else {
+    const double gy = y.s * y.c + ax * y.s - hy * y.c;
+    basin = gy > 0.0 ? 2 : (gy < 0.0 ? 1 : 0);
+  }
+  if (basin == 0) {  // on a maximum: the lower minimum, then the nearer, then the smaller angle
+    if (e1 != e2b) {
+      basin = e1 < e2b ? 1 : 2;
+    } else {
+      const double t0 = atan2(d0.s, d0.c);
+      const double t1 = atan2(u1.s, u1.c), t2 = atan2(u2.s, u2.c);
+      const double dd1 = fabs(wrap_pi(t0 - t1)), dd2 = fabs(wrap_pi(t0 - t2));
+      basin = ((dd1 < dd2) || (dd1 == dd2 && t1 <= t2)) ? 1 : 2;
+    }
+  }
+  const bool to1 = basin == 1;
+  r.two = true;
+  r.e_c = to1 ? e1 : e2b;
+  r.e_o = to1 ? e2b : e1;
+  r.e3 = e2a;
+  r.s_c = to1 ? u1.s : u2.s;
+  r.c_c = to1 ? u1.c : u2.c;
+  r.s_o = to1 ? u2.s : u1.s;
+  r.c_o = to1 ? u2.c : u1.c;
+  return r;
+}
+
 __device__ SWState sw_fall(double hx, double hy, Dir d0) {
   SWState r;
   // ---- exact special cases (field along or across the axis) ----
@@ -270,103 +431,15 @@ __device__ SWState sw_fall(double hx, double hy, Dir d0) {
     }
     return r;
   }
-  // ---- general case: reflect into hx > 0 (theta -> pi - theta flips the cosine) ----
-  const bool refl = hx < 0.0;
-  const double ax = fabs(hx);
-  const float axf = (float)ax, hyf = (float)hy;
-  const float kPiF = (float)kPi, kHalfPiF = (float)kHalfPi;
-  const Dir east{0.0, 1.0}, north{1.0, 0.0}, west{0.0, -1.0};  // angles 0, pi/2, pi
-  // FP32 starts from the small-field linearisations of g about 0 (r1 = hy / (1 + hx)) and
-  // of g' about 3 pi / 4 (t* = 3 pi / 4 + (hx - hy) / (2 sqrt 2))
-  float fs, fc;
-  seed_root<false>(0.f, kHalfPiF, true, axf, hyf, hyf * __builtin_amdgcn_rcpf(1.f + axf), fs, fc);
-  const Dir d1 = polish_root<false>(east, north, true, ax, hy, unit(fs, fc));  // global min
-  const double e1 = sw_energy(d1.s, d1.c, ax, hy);
-  bool two = false;
+  const SWArgs a = sw_args(hx, hy);
+  const Dir d1 = sw_min1(a);
+  const SWT t = sw_tstar(a);
   Dir d2a{0.0, 0.0}, d2b{0.0, 0.0};
-  double e2a = 0.0, e2b = 0.0;
-  if (astroid_bistable(ax, hy)) {
-    // a direction between the saddle maximum and the metastable minimum in (pi/2, pi):
-    // the FP32 zero t* of g', kept when g < 0 there in double precision, else polished
-    float ts = seed_root<true>(kHalfPiF, kPiF, true, axf, hyf,
-                               0.75f * kPiF + 0.35355339f * (axf - hyf), fs, fc);
-    Dir dt = unit(fs, fc);
-    if (!(dt.s > 0.0 && dt.c < 0.0 && ts > kHalfPiF && ts < kPiF)) {
-      ts = 0.75f * kPiF;
-      dt = unit(1.0, -1.0);
-    }
-    double gt = dt.s * dt.c + ax * dt.s - hy * dt.c;
-    if (!(gt < 0.0)) {
-      dt = polish_root<true>(north, west, true, ax, hy, dt);
-      gt = dt.s * dt.c + ax * dt.s - hy * dt.c;
-      ts = atan2f((float)dt.s, (float)dt.c);
-    }
-    if (gt < 0.0) {
-      two = true;
-      // starts at t* -+ sqrt(-2 g / g''), the zeros of g's quadratic expansion about its
-      // minimum t* (exact as the pair merges at the astroid)
-      float g2;
-      const float st = (float)dt.s, ct = (float)dt.c;
-      const float g0 = sw_fn<false>(st, ct, axf, hyf, g2);
-      sw_fn<true>(st, ct, axf, hyf, g2);
-      const float q = sqrtf(-2.f * g0 * __builtin_amdgcn_rcpf(g2));
-      seed_root<false>(kHalfPiF, ts, false, axf, hyf, ts - q, fs, fc);
-      d2a = polish_root<false>(north, dt, false, ax, hy, unit(fs, fc));  // saddle maximum
-      seed_root<false>(ts, kPiF, true, axf, hyf, ts + q, fs, fc);
-      d2b = polish_root<false>(dt, west, true, ax, hy, unit(fs, fc));  // metastable minimum
-      e2a = sw_energy(d2a.s, d2a.c, ax, hy);
-      e2b = sw_energy(d2b.s, d2b.c, ax, hy);
-    }
+  if (t.two) {
+    d2a = sw_saddle(a, t);
+    d2b = sw_meta(a, t);
   }
-  const Dir u1{d1.s, refl ? -d1.c : d1.c};  // unreflected directions
-  if (!two) {
-    r.two = false;
-    r.e_c = r.e_o = e1;
-    r.e3 = 0.0;
-    r.s_c = r.s_o = u1.s;
-    r.c_c = r.c_o = u1.c;
-    return r;
-  }
-  const Dir u2{d2b.s, refl ? -d2b.c : d2b.c};
-  // Basin of theta0. In the reflected frame (angle y, sine sr, cosine cr) the circle
-  // reads r1 (min) < r2a (max) < r2b (min) < r3 (max) < r1 + 2 pi with r1 in (0, pi/2),
-  // r2a and r2b in (pi/2, pi) and r3 in (pi, 3 pi/2):
-  //   cr >= 0           y in [-pi/2, pi/2], before r2a: minimum r1;
-  //   cr < 0, sr >= 0   y in (pi/2, pi]: before r2a iff sin(r2a - y) > 0;
-  //   cr < 0, sr < 0    y in (pi, 3 pi/2): before r3 iff g(y) > 0, as r3 is the only
-  //                     zero of g there and g(pi) = hy > 0 > -ax = g(3 pi/2).
-  // A zero sine or g puts the moment on a maximum (basin 0).
-  const Dir y{d0.s, refl ? -d0.c : d0.c};
-  int basin;  // 1: r1, 2: r2b, 0: on a maximum
-  if (y.c >= 0.0) {
-    basin = 1;
-  } else if (y.s >= 0.0) {
-    const double x = cross(y, d2a);
-    basin = x > 0.0 ? 1 : (x < 0.0 ? 2 : 0);
-  } else {
-    const double gy = y.s * y.c + ax * y.s - hy * y.c;
-    basin = gy > 0.0 ? 2 : (gy < 0.0 ? 1 : 0);
-  }
-  if (basin == 0) {  // on a maximum: the lower minimum, then the nearer, then the smaller angle
-    if (e1 != e2b) {
-      basin = e1 < e2b ? 1 : 2;
-    } else {
-      const double t0 = atan2(d0.s, d0.c);
-      const double t1 = atan2(u1.s, u1.c), t2 = atan2(u2.s, u2.c);
-      const double dd1 = fabs(wrap_pi(t0 - t1)), dd2 = fabs(wrap_pi(t0 - t2));
-      basin = ((dd1 < dd2) || (dd1 == dd2 && t1 <= t2)) ? 1 : 2;
-    }
-  }
-  const bool to1 = basin == 1;
-  r.two = true;
-  r.e_c = to1 ? e1 : e2b;
-  r.e_o = to1 ? e2b : e1;
-  r.e3 = e2a;
-  r.s_c = to1 ? u1.s : u2.s;
-  r.c_c = to1 ? u1.c : u2.c;
-  r.s_o = to1 ? u2.s : u1.s;
-  r.c_o = to1 ? u2.c : u1.c;
-  return r;
+  return sw_finish(a, d0, d1, t.two, d2a, d2b);
 }
 
 // Steps iv-v with step iv as the paper states it (200-point scan, Newton refinement)
@@ -623,6 +696,11 @@ __device__ __forceinline__ void transition_pair(const NPParams& p, double a_c, d
   P_oc = (xo * r) * q;
 }
 
+__device__ __forceinline__ NPResult np_finish(const NPParams& p, const Plane& w,
+                                              const SWState& sw, double nx, double ny,
+                                              double nz, uint64_t seed, uint64_t stream,
+                                              int64_t i, int64_t k);
+
 // kScan: the kernel also serves systems whose step iv is the 200-point scan (p.scan200);
 // without it that search is not compiled in, so the exact path keeps its registers.
 template <bool kScan = false>
@@ -651,6 +729,17 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
   // steps iv-v
   const SWState sw = (kScan && p.scan200) ? sw_fall_scan200(w.hx, w.hy, w.d0)
                                           : sw_fall(w.hx, w.hy, w.d0);
+  return np_finish(p, w, sw, nx, ny, nz, seed, stream, i, k);
+}
+
+// Steps vi-vii and the new moment, from the working plane and the fall (K > 0).
+__device__ __forceinline__ NPResult np_finish(const NPParams& p, const Plane& w,
+                                              const SWState& sw, double nx, double ny,
+                                              double nz, uint64_t seed, uint64_t stream,
+                                              int64_t i, int64_t k) {
+  NPResult out;
+  out.P = 0.0;
+  out.jump = 0;
   double s = sw.s_c, c = sw.c_c;
   out.two = sw.two;
   // steps vi-vii

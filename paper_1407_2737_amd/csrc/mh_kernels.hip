@@ -381,6 +381,96 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
   }
 }
 
+// Launches of at most this many 256-particle blocks use k_update3 (one block per CU).
+constexpr int kUpdate3MaxBlocks = 256;
+
+// Per-particle update with the roots of the fall spread over three waves per particle
+// (exact extremum search). A block holds 256 particles and 768 threads in three roles
+// of four waves: role 0 finds the global minimum, role 1 t* and the saddle, role 2 t*
+// and the metastable minimum, for the same particles; the roles meet in LDS and role 0
+// finishes steps v-vii and writes the outputs. On a launch with fewer waves than SIMDs
+// the three chains run side by side, so a step waits for the longest of them instead of
+// their sum. Each piece is the one sw_fall runs, so the results are those of k_update.
+// Special cases (field along or across the axis, K = 0, diagnostics) run whole on role 0.
+__global__ __launch_bounds__(768) void k_update3(const SysDesc* __restrict__ systems,
+                                                 const int2* __restrict__ blocks,
+                                                 const int64_t* __restrict__ kbase,
+                                                 int64_t koff) {
+  __shared__ double red[12];
+  __shared__ double2 sh_r2a[256], sh_r2b[256];
+  __shared__ int sh_two[256];
+  const int2 bl = blocks[blockIdx.x];
+  const SysDesc& s = systems[bl.x];
+  const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
+  if (k < 0 || k >= s.total_steps) return;                      // uniform over the block
+  const int role = threadIdx.x >> 8, t = threadIdx.x & 255;
+  const int i = bl.y * 256 + t;
+  const int cur = (int)(k & 1);
+  const bool act = i < s.n;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  bool general = false;
+  NPIn q;
+  Plane w;
+  SWArgs a;
+  Dir d1{0.0, 0.0};
+  if (act) {
+    for (int p = 0; p < s.nsplit; ++p) {  // partial sums of the source parts, fixed order
+      const D4 f = s.field[(int64_t)p * s.n + i];
+      fx += f.x;
+      fy += f.y;
+      fz += f.z;
+    }
+    if (!s.field_only && s.np.aniso) {
+      q = np_in(s, i, k, cur, fx, fy, fz);
+      w = working_plane(s.np, q.Bx, q.By, q.Bz, q.nn.x, q.nn.y, q.nn.z, q.mo.x, q.mo.y, q.mo.z);
+      general = w.hy != 0.0 && w.hx != 0.0;
+    }
+    if (general) {
+      a = sw_args(w.hx, w.hy);
+      if (role == 0) {
+        d1 = sw_min1(a);
+      } else {
+        const SWT tt = sw_tstar(a);
+        if (role == 1) {
+          sh_two[t] = tt.two ? 1 : 0;
+          if (tt.two) {
+            const Dir d = sw_saddle(a, tt);
+            sh_r2a[t] = make_double2(d.s, d.c);
+          }
+        } else if (tt.two) {
+          const Dir d = sw_meta(a, tt);
+          sh_r2b[t] = make_double2(d.s, d.c);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  double mx = 0.0;
+  if (role == 0 && act) {
+    if (general) {
+      np_dhdip(s, i, k, fx, fy, fz);
+      const bool two = sh_two[t] != 0;
+      const Dir d2a = two ? Dir{sh_r2a[t].x, sh_r2a[t].y} : Dir{0.0, 0.0};
+      const Dir d2b = two ? Dir{sh_r2b[t].x, sh_r2b[t].y} : Dir{0.0, 0.0};
+      const SWState sw = sw_finish(a, w.d0, d1, two, d2a, d2b);
+      const NPResult r =
+          np_finish(s.np, w, sw, q.nn.x, q.nn.y, q.nn.z, s.seed, s.stream, i, k);
+      mx = np_out(s, i, k, cur, q, r);
+    } else {
+      mx = np_epilogue<false>(s, i, k, cur, fx, fy, fz);
+    }
+  }
+  if (k >= s.kept0 && !s.field_only) {  // uniform over the block
+    double v = role == 0 ? mx : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      s.recpart[(k - s.kept0) * s.ntiles + bl.y] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // End of run: per-system loop record and area, per-assembly replica statistics.
 // ---------------------------------------------------------------------------
@@ -683,9 +773,15 @@ hipError_t launch_field(bool fp64, int kind, int G, const SysDesc* d_sys, const 
 hipError_t launch_update(bool scan, const SysDesc* d_sys, const int2* d_blocks, int nblocks,
                          const int64_t* kbase, int64_t koff, hipStream_t st) {
   if (nblocks == 0) return hipSuccess;
+  // the three-role form pays while the blocks leave CUs idle; beyond that its duplicated
+  // work (plane and t* on three and two waves) costs more than the shorter chains save.
+  // Both forms compute the same pieces in the same order, so the choice does not change
+  // results (tested across the threshold)
   if (scan)
     hipLaunchKernelGGL(k_update<true>, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase,
                        koff);
+  else if (nblocks <= kUpdate3MaxBlocks)
+    hipLaunchKernelGGL(k_update3, dim3(nblocks), dim3(768), 0, st, d_sys, d_blocks, kbase, koff);
   else
     hipLaunchKernelGGL(k_update<false>, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase,
                        koff);

@@ -60,38 +60,47 @@ __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {
   return s.Bmax * cos(2.0 * kPi * (double)k / (double)s.S);
 }
 
-// Steps iii-vii for particle i of system s with the reduced dipolar sum (ax, ay, az)
-// from the moments in buffer cur; writes buffer cur^1, accumulates the area, and
-// returns the new moment's component along the field direction e_H. kScan as for
-// np_update.
-template <bool kScan>
-__device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur, double ax, double ay,
-                              double az) {
-  if (s.field_only) {
-    double* d = s.diag + (int64_t)i * 8;
-    d[0] = s.Bscale * ax;
-    d[1] = s.Bscale * ay;
-    d[2] = s.Bscale * az;
-    return 0.0;
-  }
-  const double Bext = applied_field(s, k);
+// Inputs of steps iii-vii for particle i of system s from the reduced dipolar sum
+// (ax, ay, az) and the moments of buffer cur: the applied and total field, the moment
+// and the axis.
+struct NPIn {
+  double Bext, Bx, By, Bz;
+  D4 mo, nn;
+};
+
+__device__ __forceinline__ NPIn np_in(const SysDesc& s, int i, int64_t k, int cur, double ax,
+                                      double ay, double az) {
+  NPIn q;
+  q.Bext = applied_field(s, k);
   const double ex = s.eh[0], ey = s.eh[1], ez = s.eh[2];
-  const double Bx = s.Bscale * ax + Bext * ex, By = s.Bscale * ay + Bext * ey,
-               Bz = s.Bscale * az + Bext * ez;
+  q.Bx = s.Bscale * ax + q.Bext * ex;
+  q.By = s.Bscale * ay + q.Bext * ey;
+  q.Bz = s.Bscale * az + q.Bext * ez;
+  q.mo = s.m64[(int64_t)cur * s.stride + i];
+  q.nn = s.axes[i];
+  return q;
+}
+
+// Eq. 6: the dipolar field along e_H in the +Hmax step (k = 0 mod S) minus that in the
+// -Hmax step (k = S/2 mod S), over the kept periods.
+__device__ __forceinline__ void np_dhdip(const SysDesc& s, int i, int64_t k, double ax, double ay,
+                                         double az) {
   if (s.dhdip && k >= s.kept0) {
-    // Eq. 6: the dipolar field along e_H in the +Hmax step (k = 0 mod S) minus that in
-    // the -Hmax step (k = S/2 mod S)
     const int64_t ph = k % s.S;
+    const double ex = s.eh[0], ey = s.eh[1], ez = s.eh[2];
     const double bh = s.Bscale * ax * ex + s.Bscale * ay * ey + s.Bscale * az * ez;
     if (ph == 0)
       s.dhdip[i] += bh;
     else if (ph == s.S / 2)
       s.dhdip[i] -= bh;
   }
-  const D4 mo = s.m64[(int64_t)cur * s.stride + i];
-  const D4 nn = s.axes[i];
-  const NPResult r =
-      np_update<kScan>(s.np, Bx, By, Bz, nn.x, nn.y, nn.z, mo.x, mo.y, mo.z, s.seed, s.stream, i, k);
+}
+
+// Outputs of the step: the new moment into buffer cur^1 (and its FP32 copy), the area,
+// the diagnostics; returns the new moment's component along e_H.
+__device__ __forceinline__ double np_out(const SysDesc& s, int i, int64_t k, int cur,
+                                         const NPIn& q, const NPResult& r) {
+  const double ex = s.eh[0], ey = s.eh[1], ez = s.eh[2];
   const int nxt = cur ^ 1;
   D4 mn;
   mn.x = r.mx;
@@ -109,17 +118,18 @@ __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur
   }
   const double mh_new = r.mx * ex + r.my * ey + r.mz * ez;
   if (k >= s.kept0) {
+    const D4& mo = q.mo;
     const double mh_old = mo.x * ex + mo.y * ey + mo.z * ez;
     double sum = s.area[i], comp = s.area[s.n + i];
-    neumaier_add(sum, comp, s.Ms * Bext * (mh_new - mh_old));
+    neumaier_add(sum, comp, s.Ms * q.Bext * (mh_new - mh_old));
     s.area[i] = sum;
     s.area[s.n + i] = comp;
   }
   if (s.diag) {
     double* d = s.diag + (int64_t)i * 8;
-    d[0] = Bx;
-    d[1] = By;
-    d[2] = Bz;
+    d[0] = q.Bx;
+    d[1] = q.By;
+    d[2] = q.Bz;
     d[3] = r.P;
     d[4] = (double)r.jump;
     d[5] = (double)r.two;
@@ -127,6 +137,27 @@ __device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur
     d[7] = 0.0;
   }
   return mh_new;
+}
+
+// Steps iii-vii for particle i of system s with the reduced dipolar sum (ax, ay, az)
+// from the moments in buffer cur; writes buffer cur^1, accumulates the area, and
+// returns the new moment's component along the field direction e_H. kScan as for
+// np_update.
+template <bool kScan>
+__device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur, double ax, double ay,
+                              double az) {
+  if (s.field_only) {
+    double* d = s.diag + (int64_t)i * 8;
+    d[0] = s.Bscale * ax;
+    d[1] = s.Bscale * ay;
+    d[2] = s.Bscale * az;
+    return 0.0;
+  }
+  np_dhdip(s, i, k, ax, ay, az);
+  const NPIn q = np_in(s, i, k, cur, ax, ay, az);
+  const NPResult r = np_update<kScan>(s.np, q.Bx, q.By, q.Bz, q.nn.x, q.nn.y, q.nn.z, q.mo.x,
+                                      q.mo.y, q.mo.z, s.seed, s.stream, i, k);
+  return np_out(s, i, k, cur, q, r);
 }
 
 }  // namespace mh

@@ -64,3 +64,31 @@ def test_batch_equals_alone(lib):
     for q, a in enumerate(asms):
         a.sync()
         assert np.array_equal(a.replica_areas(), alone[q][0]), q
+
+
+def test_update_forms_agree_across_the_launch_threshold(lib):
+    """A small tiled assembly alone launches the three-role update kernel (few blocks);
+    batched with a large one, the launch exceeds 256 blocks and uses the single-role
+    kernel. Its results must be bitwise the same either way, in FP32 and FP64."""
+    ctx = lib.Context(0)
+    kw = dict(Ms=4e5, Keff=1.3e4, d=12e-9, T=300.0, tau0=1e-10, rho=5200.0, f=1e5,
+              mu0Hmax=0.02, steps_per_period=100, n_periods=2, n_discard=1)
+    for prec in (lib.FP32_FIELD, lib.FP64):
+        pos = W.place_random(1500, 120e-9, 12e-9, 71)
+        axes = W.axes_random_3d(1500, 72)
+        small = lib.Assembly(ctx, pos, axes, lib.Params.make(prec, **kw))
+        small.run(3, seed=5)
+        small.sync()
+        alone = (small.replica_areas().copy(), small.moments(2).copy(),
+                 small.loop(1, 0)[1].copy())
+        pos2 = W.place_random(4000, 170e-9, 12e-9, 73)
+        big = lib.Assembly(ctx, pos2, W.axes_random_3d(4000, 74),
+                           lib.Params.make(lib.FP32_FIELD, **kw))
+        lib.run_batch([small, big], [3, 80], [5, 6])   # 3 x 6 + 80 x 16 = 1298 update blocks
+        small.sync()
+        big.sync()
+        assert np.array_equal(small.replica_areas(), alone[0])
+        assert np.array_equal(small.moments(2), alone[1])
+        assert np.array_equal(small.loop(1, 0)[1], alone[2])
+        small.close()
+        big.close()
