@@ -1,0 +1,78 @@
+"""Parity at full benchmark size, in the launch configuration the benchmarks time, on
+outputs the FP64 oracle computes directly:
+
+* config 2: one assembly of N = 5000 (250 nm lysosome, d = 12 nm), FP32 field, three
+  replicas at 10, 20 and 40 mT set as per-replica amplitudes. One step from a random
+  snapshot at two step indices, every particle of every replica against the oracle.
+* config 4: N = 4096 at phi = 10 %, 512 replicas with one axis set each, BF16x3 matrix
+  form. One step of all 512 replicas from a random snapshot; four sampled replicas
+  against the oracle.
+
+Fields are held to the precision's bound (relative Frobenius 1e-5 for FP32, 1e-4 for
+BF16x3, whose measured error is about 3e-6). A jump decision may differ only where the
+draw u lies within the field-induced error of P. New moments must agree wherever the
+decisions do."""
+import numpy as np
+import pytest
+
+from oracle import kmc
+from paper_1407_2737_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.Context(0)
+
+
+def _unit(shape, seed):
+    m = np.random.default_rng(seed).normal(size=shape + (3,))
+    return m / np.linalg.norm(m, axis=-1, keepdims=True)
+
+
+def _check_step(diag_r, m_gpu, m_new, info, field_tol, p_tol):
+    B = diag_r[:, :3]
+    err = np.linalg.norm(B - info.B) / np.linalg.norm(info.B)
+    assert err < field_tol, err
+    dif = (diag_r[:, 4] == 1.0) != info.jump
+    assert np.all((np.abs(info.u - info.P) < p_tol)[dif]), np.count_nonzero(dif)
+    same = ~dif
+    assert np.abs(m_gpu[same] - m_new[same]).max() < 1e-3
+    return err, int(np.count_nonzero(dif))
+
+
+def test_config2_full_size_step(ctx, lib):
+    w2 = W.config2()
+    amps = (0.010, 0.020, 0.040)
+    a = lib.Assembly(ctx, w2.pos, w2.axes, lib.params_from_material(w2.mat, lib.FP32_FIELD))
+    a.set_replica_fields(list(amps))
+    m_in = _unit((len(amps), w2.n), 300)
+    for k in (0, 4321):
+        diag = a.debug_steps(len(amps), w2.seed, k, k + 1, m_in.reshape(-1, 3))
+        for r, h in enumerate(amps):
+            pk = kmc.Params.from_dict(dict(w2.mat.as_dict(), mu0Hmax=h))
+            m_new, info = kmc.step(w2.pos, w2.axes, m_in[r], k, pk, w2.seed, r)
+            err, nd = _check_step(diag[r], a.moments(r), m_new, info, 1e-5, 1e-4)
+            print(f"config 2, k={k}, {h * 1e3:g} mT: field error {err:.2e}, "
+                  f"{nd} decisions differ, {int(info.jump.sum())} jumps")
+    a.close()
+
+
+def test_config4_full_size_step_sampled_replicas(ctx, lib):
+    R = 512
+    a4 = W.config4(n_axes_sets=R)
+    n = a4.n
+    a = lib.Assembly(ctx, a4.pos, a4.axes, lib.params_from_material(a4.mat, lib.BF16X3_WM),
+                     n_axes_sets=R)
+    m_in = _unit((R, n), 400)
+    k = 1500
+    diag = a.debug_steps(R, a4.seed, k, k + 1, m_in.reshape(-1, 3))
+    pk = kmc.Params.from_dict(a4.mat.as_dict())
+    for r in (0, 137, 300, 511):
+        axes_r = a4.axes[r * n:(r + 1) * n]
+        m_new, info = kmc.step(a4.pos, axes_r, m_in[r], k, pk, a4.seed, r)
+        err, nd = _check_step(diag[r], a.moments(r), m_new, info, 1e-4, 1e-3)
+        print(f"config 4, replica {r}: field error {err:.2e}, {nd} decisions differ, "
+              f"{int(info.jump.sum())} jumps")
+    a.close()
