@@ -54,19 +54,6 @@ __device__ __forceinline__ F4* mom_of<float>(const SysDesc& s) {
   return s.m32;
 }
 
-// Load through the global address space as one vector (the pointers come from
-// descriptors in memory, where the compiler cannot infer it and would emit flat loads).
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef double d4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ F4 ldg(const F4* p) {
-  const f4v v = *(const __attribute__((address_space(1))) f4v*)p;
-  return F4{v.x, v.y, v.z, v.w};
-}
-__device__ __forceinline__ D4 ldg(const D4* p) {
-  const d4v v = *(const __attribute__((address_space(1))) d4v*)p;
-  return D4{v.x, v.y, v.z, v.w};
-}
-
 // 1/r for a squared distance in units of d. Distinct particles are at least one
 // diameter apart and padding sits at 1e15, so r2 is 0 (the pair j == i, masked by the
 // caller) or a normal number: the hardware reciprocal square root needs none of the
@@ -260,7 +247,9 @@ __global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ s
   P4 (*smom)[CH] = reinterpret_cast<P4 (*)[CH]>(lds + sizeof(P4) * CH);
   T (*red)[G][Q][TI] = reinterpret_cast<T (*)[G][Q][TI]>(lds);     // after the last chunk
   double (*part)[G][NPART][TI] = reinterpret_cast<double (*)[G][NPART][TI]>(lds + kRed);
-  const int4 tl = tiles[blockIdx.x];               // (first system, i-tile, replicas, part)
+  const int4 tlv = tiles[blockIdx.x];  // (first system, i-tile, replicas, part), uniform
+  const int4 tl = make_int4(__builtin_amdgcn_readfirstlane(tlv.x), __builtin_amdgcn_readfirstlane(tlv.y),
+                            __builtin_amdgcn_readfirstlane(tlv.z), __builtin_amdgcn_readfirstlane(tlv.w));
   const SysDesc& s = systems[tl.x];
   const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;
@@ -384,7 +373,11 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
                                                 const int2* __restrict__ blocks,
                                                 const int64_t* __restrict__ kbase, int64_t koff) {
   __shared__ double red[4];
-  const int2 bl = blocks[blockIdx.x];
+  // the block's (system, particle block) is uniform: keep it in scalar registers, so the
+  // descriptor is read with scalar loads and data loads are not chained behind it
+  const int2 blv = blocks[blockIdx.x];
+  const int2 bl = make_int2(__builtin_amdgcn_readfirstlane(blv.x),
+                            __builtin_amdgcn_readfirstlane(blv.y));
   const SysDesc& s = systems[bl.x];
   const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;
@@ -392,19 +385,22 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
   const int cur = (int)(k & 1);
   double mx = 0.0;
   if (i < s.n) {
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int p = 0; p < s.nsplit; ++p) {  // partial sums of the source parts, fixed order
-      const D4 f = s.field[(int64_t)p * s.n + i];
-      fx += f.x;
-      fy += f.y;
-      fz += f.z;
-    }
+    double fx, fy, fz;
+    sum_parts(s, i, fx, fy, fz);  // partial sums of the source parts, fixed order
     mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz);
   }
   if (k >= s.kept0 && !s.field_only) {
     const double tot = block_sum_256(mx, red);
     if (threadIdx.x == 0) s.recpart[(k - s.kept0) * s.ntiles + bl.y] = tot;
   }
+}
+
+// The special cases of k_update3 (field along or across the axis, K = 0, diagnostics)
+// out of line: kept apart, the role paths schedule as a small kernel (measured: inlining
+// it slowed config 2's update from 11.9 to 12.3 us).
+__device__ __noinline__ double np_epilogue_rare(const SysDesc& s, int i, int64_t k, int cur,
+                                                double ax, double ay, double az) {
+  return np_epilogue<false>(s, i, k, cur, ax, ay, az);
 }
 
 // Launches of at most this many 256-particle blocks use k_update3 (one block per CU).
@@ -425,7 +421,11 @@ __global__ __launch_bounds__(768) void k_update3(const SysDesc* __restrict__ sys
   __shared__ double red[12];
   __shared__ double2 sh_r2a[256], sh_r2b[256];
   __shared__ int sh_two[256];
-  const int2 bl = blocks[blockIdx.x];
+  // the block's (system, particle block) is uniform: keep it in scalar registers, so the
+  // descriptor is read with scalar loads and data loads are not chained behind it
+  const int2 blv = blocks[blockIdx.x];
+  const int2 bl = make_int2(__builtin_amdgcn_readfirstlane(blv.x),
+                            __builtin_amdgcn_readfirstlane(blv.y));
   const SysDesc& s = systems[bl.x];
   const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;                      // uniform over the block
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(768) void k_update3(const SysDesc* __restrict__ sys
           np_finish(s.np, w, sw, q.nn.x, q.nn.y, q.nn.z, s.seed, s.stream, i, k);
       mx = np_out(s, i, k, cur, q, r);
     } else {
-      mx = np_epilogue<false>(s, i, k, cur, fx, fy, fz);
+      mx = np_epilogue_rare(s, i, k, cur, fx, fy, fz);
     }
   }
   if (k >= s.kept0 && !s.field_only) {  // uniform over the block

@@ -60,6 +60,20 @@ __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {
   return s.Bmax * cos(2.0 * kPi * (double)k / (double)s.S);
 }
 
+// Loads through the global address space as one vector. The pointers come from
+// descriptors in memory, where the compiler cannot infer the address space and would
+// emit flat loads, whose waits also wait on LDS and scalar loads.
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ F4 ldg(const F4* p) {
+  const f4v v = *(const __attribute__((address_space(1))) f4v*)p;
+  return F4{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ D4 ldg(const D4* p) {
+  const d4v v = *(const __attribute__((address_space(1))) d4v*)p;
+  return D4{v.x, v.y, v.z, v.w};
+}
+
 // Inputs of steps iii-vii for particle i of system s from the reduced dipolar sum
 // (ax, ay, az) and the moments of buffer cur: the applied and total field, the moment
 // and the axis.
@@ -68,17 +82,51 @@ struct NPIn {
   D4 mo, nn;
 };
 
-__device__ __forceinline__ NPIn np_in(const SysDesc& s, int i, int64_t k, int cur, double ax,
-                                      double ay, double az) {
+__device__ __forceinline__ NPIn np_in(const SysDesc& s, int64_t k, double ax, double ay,
+                                      double az, const D4& mo, const D4& nn) {
   NPIn q;
   q.Bext = applied_field(s, k);
   const double ex = s.eh[0], ey = s.eh[1], ez = s.eh[2];
   q.Bx = s.Bscale * ax + q.Bext * ex;
   q.By = s.Bscale * ay + q.Bext * ey;
   q.Bz = s.Bscale * az + q.Bext * ez;
-  q.mo = s.m64[(int64_t)cur * s.stride + i];
-  q.nn = s.axes[i];
+  q.mo = mo;
+  q.nn = nn;
   return q;
+}
+
+__device__ __forceinline__ NPIn np_in(const SysDesc& s, int i, int64_t k, int cur, double ax,
+                                      double ay, double az) {
+  return np_in(s, k, ax, ay, az, s.m64[(int64_t)cur * s.stride + i], s.axes[i]);
+}
+
+// Sum of the nsplit partial fields of particle i in part order. The loads of four parts
+// at a time are issued together (addresses of missing parts fall back to part 0 and
+// their terms are skipped), so a few parts cost one memory round trip, not one each.
+__device__ __forceinline__ void sum_parts(const SysDesc& s, int i, double& fx, double& fy,
+                                          double& fz) {
+  fx = fy = fz = 0.0;
+  const int64_t n = s.n;
+  for (int p0 = 0; p0 < s.nsplit; p0 += 4) {
+    const D4* b = s.field + (int64_t)p0 * n + i;
+    const int m = s.nsplit - p0;
+    const D4 f0 = ldg(b);
+    const D4 f1 = ldg(b + (m > 1 ? n : 0));
+    const D4 f2 = ldg(b + (m > 2 ? 2 * n : 0));
+    const D4 f3 = ldg(b + (m > 3 ? 3 * n : 0));
+    fx += f0.x;
+    fy += f0.y;
+    fz += f0.z;
+    fx = m > 1 ? fx + f1.x : fx;
+    fy = m > 1 ? fy + f1.y : fy;
+    fz = m > 1 ? fz + f1.z : fz;
+    fx = m > 2 ? fx + f2.x : fx;
+    fy = m > 2 ? fy + f2.y : fy;
+    fz = m > 2 ? fz + f2.z : fz;
+    fx = m > 3 ? fx + f3.x : fx;
+    fy = m > 3 ? fy + f3.y : fy;
+    fz = m > 3 ? fz + f3.z : fz;
+  }
 }
 
 // Eq. 6: the dipolar field along e_H in the +Hmax step (k = 0 mod S) minus that in the
@@ -144,8 +192,8 @@ __device__ __forceinline__ double np_out(const SysDesc& s, int i, int64_t k, int
 // returns the new moment's component along the field direction e_H. kScan as for
 // np_update.
 template <bool kScan>
-__device__ inline double np_epilogue(const SysDesc& s, int i, int64_t k, int cur, double ax, double ay,
-                              double az) {
+__device__ __forceinline__ double np_epilogue(const SysDesc& s, int i, int64_t k, int cur,
+                                              double ax, double ay, double az) {
   if (s.field_only) {
     double* d = s.diag + (int64_t)i * 8;
     d[0] = s.Bscale * ax;
