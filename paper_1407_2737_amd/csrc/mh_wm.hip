@@ -73,7 +73,8 @@ __device__ __forceinline__ void split_pack(float a, float b, uint32_t& hi, uint3
 }
 
 // The 3x3 block T_ij (reduced units) of target position p and source q: q.w = 0 marks
-// a missing source (padding), own = the target itself. Row a of the block in t[3a..].
+// a missing source (padding), own = the target itself. Row a of the block in t[3a..];
+// the block is symmetric, so its six distinct entries are computed once.
 __device__ __forceinline__ void pair_block(double px, double py, double pz, bool tgt_ok,
                                            const D4& q, bool own, float* t) {
   const bool ok = tgt_ok && q.w != 0.0 && !own;
@@ -85,13 +86,10 @@ __device__ __forceinline__ void pair_block(double px, double py, double pz, bool
   const float s5 = 3.0f * c3 * inv2;
   const float ux = dx * s5, uy = dy * s5, uz = dz * s5;
   t[0] = dx * ux - c3;
-  t[1] = dx * uy;
-  t[2] = dx * uz;
-  t[3] = dy * ux;
+  t[1] = t[3] = dx * uy;
+  t[2] = t[6] = dx * uz;
   t[4] = dy * uy - c3;
-  t[5] = dy * uz;
-  t[6] = dz * ux;
-  t[7] = dz * uy;
+  t[5] = t[7] = dy * uz;
   t[8] = dz * uz - c3;
 }
 
