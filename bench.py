@@ -34,7 +34,7 @@ MOMENT_FLOPS = 18               # per replica: 5 for m.r, 1 scale, 4 per compone
 # WRITE_SIZE over the default workload (one period), each scaled by what the counter
 # reads for a 256 MiB elementwise copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).
 # Tied to the kernel as measured: k_field<float,16,3> with three source parts per tile
-# (profiles/k_field_config2_fp32.md); None for kernels without such a measurement.
+# (profiles/k_field_n5000x3_fp32.md); None for kernels without such a measurement.
 TRAFFIC_BYTES = {"k_field<float,16,3>": (1347.44 * 2.000 + 1406.25 * 1.000) * 1024}
 
 
@@ -64,9 +64,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="config 3: built-in launch-shape rule")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c4plain", "c5", "c5wm", "master", "sweep",
-                             "methods", "figs"])
+    ap.add_argument("--no-tune", action="store_true", help="uneven256: built-in launch-shape rule")
+    ap.add_argument("--workload", default="n5000",
+                    choices=["n100", "n5000", "uneven256", "replicas512", "replicas512plain",
+                             "served", "servedwm", "master", "sweep", "methods", "figs"])
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--max-replicas", type=int, default=64)
     ap.add_argument("--assemblies", type=int, default=256)
@@ -81,25 +82,25 @@ def main():
     import paper_1407_2737_amd as mh
     from paper_1407_2737_amd import workloads as W
 
-    if args.workload == "c3":
-        return bench_c3(args, mh, W)
+    if args.workload == "uneven256":
+        return bench_uneven256(args, mh, W)
     if args.workload == "master":
         return bench_master(args, mh, W)
-    if args.workload == "c1":
-        return bench_c1(args, mh, W)
+    if args.workload == "n100":
+        return bench_n100(args, mh, W)
     if args.workload == "sweep":
         return bench_sweep(args, mh, W)
     if args.workload == "methods":
         return bench_methods(args, mh, W)
     if args.workload == "figs":
         return bench_figs(args, mh, W)
-    if args.workload in ("c5", "c5wm"):
-        return bench_c5(args, mh, W)
-    if args.workload != "c2":
-        return bench_c4(args, mh, W)
+    if args.workload in ("served", "servedwm"):
+        return bench_served(args, mh, W)
+    if args.workload != "n5000":
+        return bench_replicas512(args, mh, W)
 
     amps = (0.010, 0.020, 0.040)
-    w2 = W.config2(n_periods=args.periods)
+    w2 = W.lysosome_n5000(n_periods=args.periods)
     work = [w2] * len(amps)
     ctx = mh.Context(0)
     # one lysosome, one replica per amplitude (Philox stream = replica index)
@@ -174,7 +175,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 field / f64 barrier",
         "data": "synthetic",
-        "config": {"workload": "config2: N=5000 in a 250 nm lysosome, d=12 nm (phi=6.9%), "
+        "config": {"workload": "N=5000 in a 250 nm lysosome, d=12 nm (phi=6.9%), "
                                "random 3-D axes, 10/20/40 mT batched, 100 kHz, "
                                f"{args.periods} periods x 2000 steps",
                    "n_particles_total": n_total, "steps_per_run": steps_per_run,
@@ -192,12 +193,12 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def bench_c1(args, mh, W):
-    """Config 1: N=100 in an 80 nm lysosome, FP64 end to end, 3 periods of 2000 steps.
+def bench_n100(args, mh, W):
+    """N=100 in an 80 nm lysosome, FP64 end to end, 3 periods of 2000 steps.
     One replica is a chain of 6000 dependent steps in one resident workgroup (latency:
     us per time step); 1024 replicas on their own Philox streams show the throughput of
     the same kernel."""
-    a1 = W.config1()
+    a1 = W.lysosome_n100()
     ctx = mh.Context(0)
     asm = mh.Assembly(ctx, a1.pos, a1.axes, mh.params_from_material(a1.mat, mh.FP64))
     steps_per_run = a1.mat.steps_per_period * a1.mat.n_periods
@@ -217,7 +218,7 @@ def bench_c1(args, mh, W):
             "unit": "NP·steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": out[1024] * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "config1: N=100 in an 80 nm lysosome, d=12 nm, 20 mT, 100 kHz, "
+            "config": {"workload": "N=100 in an 80 nm lysosome, d=12 nm, 20 mT, 100 kHz, "
                                    "3 periods x 2000 steps, FP64, 1024 replicas",
                        "us_per_time_step_one_replica": out[1] / steps_per_run * 1e6,
                        "sar_W_per_g": sar["sar"] / 1e3, "sar_se_W_per_g": sar["sar_se"] / 1e3},
@@ -459,7 +460,7 @@ def bench_figs(args, mh, W):
 def bench_master(args, mh, W):
     """Deterministic mean-magnetisation loops (non-interacting particles, the paper's
     validation method): 10 000 particles with random 3-D axes, 8 axis sets run together,
-    config-2 material at 20 mT, 100 kHz, --periods periods of 2000 steps. One launch per
+    material of the N = 5000 lysosome at 20 mT, 100 kHz, --periods periods of 2000 steps. One launch per
     run; value counts particle-steps of the weighted two-well state."""
     import numpy as np
     n, sets = 10000, 8
@@ -500,7 +501,7 @@ def bench_master(args, mh, W):
     print(json.dumps(line), flush=True)
 
 
-def bench_c5(args, mh, W):
+def bench_served(args, mh, W):
     """Serving: loop-simulation requests with N log-uniform in [100, 8000], radius
     U(80,300) nm, phi U(1,20) %, f log-uniform in [1e5, 1e6] Hz, Hmax U(5,50) mT, 3-10
     periods (one discarded). Phase 1 submits the first quarter at once to measure the
@@ -508,8 +509,8 @@ def bench_c5(args, mh, W):
     Each request runs rounds of replicas until 2 SE <= max(1 % |A|, 1e-3 2K) or
     --max-replicas."""
     import numpy as np
-    prec = mh.BF16X3_WM if args.workload == "c5wm" else mh.FP32_FIELD
-    reqs = W.config5_requests(count=args.requests, seed=1005, rate_hz=1.0)
+    prec = mh.BF16X3_WM if args.workload == "servedwm" else mh.FP32_FIELD
+    reqs = W.request_stream(count=args.requests, seed=1005, rate_hz=1.0)
     inputs = []
     for q in reqs:
         Rl = q["R"]
@@ -562,7 +563,7 @@ def bench_c5(args, mh, W):
             "scaling": "weak", "vs_baseline": None,
             "dtype": "bf16x3 mfma / f64 barrier" if prec == mh.BF16X3_WM else "f32 field / f64 barrier",
             "data": "synthetic",
-            "config": {"workload": f"config5 ({args.workload}): Poisson arrivals at 0.7 x saturated rate "
+            "config": {"workload": f"served request stream ({args.workload}): Poisson arrivals at 0.7 x saturated rate "
                                    f"({lam:.3f} req/s), {len(ids2)} timed requests after {n1} saturation ones",
                        "p50_latency_s": float(np.percentile(lat, 50)),
                        "p99_latency_s": float(np.percentile(lat, 99)),
@@ -574,11 +575,11 @@ def bench_c5(args, mh, W):
     print(json.dumps(line), flush=True)
 
 
-def bench_c3(args, mh, W):
+def bench_uneven256(args, mh, W):
     """Batched uneven assemblies: 256 lysosomes with R ~ U(100,250) nm, phi ~ U(1,20) %,
     d ~ U(10,16) nm, K ~ U(0.8,2)e4, Hmax ~ U(5,40) mT, N in [200, 8000], one replica
     each, FP32 field, run together."""
-    work = W.config3(count=args.assemblies, n_periods=args.periods)
+    work = W.uneven_batch(count=args.assemblies, n_periods=args.periods)
     ctx = mh.Context(0)
     tune = None
     if not args.no_tune:
@@ -627,7 +628,7 @@ def bench_c3(args, mh, W):
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32 field / f64 barrier", "data": "synthetic",
-            "config": {"workload": f"config3: {len(work)} uneven assemblies, N {min(w.n for w in work)}"
+            "config": {"workload": f"{len(work)} uneven assemblies, N {min(w.n for w in work)}"
                                    f"-{max(w.n for w in work)}, {args.periods} periods x 2000 steps",
                        "n_particles_total": sum(w.n for w in work),
                        "sar_W_per_g_median": float(sorted(sars)[len(sars) // 2]) / 1e3,
@@ -636,16 +637,16 @@ def bench_c3(args, mh, W):
     print(json.dumps(line), flush=True)
 
 
-def bench_c4(args, mh, W):
+def bench_replicas512(args, mh, W):
     """Replica-batched form: N=4096 in a 200 nm lysosome at phi=10 %, one axis set per
-    replica, R replicas on independent Philox streams; W.M on MFMA (c4) or the plain
-    FP32 N-body kernels on the same replicas (c4plain)."""
+    replica, R replicas on independent Philox streams; W.M on MFMA (replicas512) or the plain
+    FP32 N-body kernels on the same replicas (replicas512plain)."""
     import numpy as np
     R = args.replicas
-    a4 = W.config4(n_axes_sets=R)
+    a4 = W.replica_batch_n4096(n_axes_sets=R)
     a4.mat.n_periods = args.periods
     a4.mat.n_discard = min(a4.mat.n_discard, args.periods - 1)
-    prec = mh.BF16X3_WM if args.workload == "c4" else mh.FP32_FIELD
+    prec = mh.BF16X3_WM if args.workload == "replicas512" else mh.FP32_FIELD
     ctx = mh.Context(0)
     asm = mh.Assembly(ctx, a4.pos, a4.axes, mh.params_from_material(a4.mat, prec), n_axes_sets=R)
     steps_per_run = a4.mat.steps_per_period * a4.mat.n_periods
@@ -663,15 +664,15 @@ def bench_c4(args, mh, W):
     t1 = time.perf_counter()
     ctx.set_timing(True)
     one_run()
-    kind = 2 if args.workload == "c4" else 0
+    kind = 2 if args.workload == "replicas512" else 0
     ms_k, launches = ctx.get_timing(kind)
-    ms_u, lu = ctx.get_timing(4 if args.workload == "c4" else 3)
+    ms_u, lu = ctx.get_timing(4 if args.workload == "replicas512" else 3)
     ctx.set_timing(False)
     wall = t1 - t0
     n = a4.n
     value = n * R * steps_per_run * args.steps / wall
     avg = ms_k / 1e3 / max(launches, 1)
-    if args.workload == "c4":
+    if args.workload == "replicas512":
         alg = 2.0 * (3 * n) ** 2 * R          # one W.M product per step
         roof = {"bound": "mfma", "achieved": alg / avg / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
                 "frac": alg / avg / 2.5e15, "traffic": None, "kernel": "k_wm_gemm",
@@ -694,9 +695,9 @@ def bench_c4(args, mh, W):
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None,
-            "dtype": "bf16x3 mfma / f64 barrier" if args.workload == "c4" else "f32 field / f64 barrier",
+            "dtype": "bf16x3 mfma / f64 barrier" if args.workload == "replicas512" else "f32 field / f64 barrier",
             "data": "synthetic",
-            "config": {"workload": f"config4 ({args.workload}): N={n}, R={R} replicas, 200 nm, "
+            "config": {"workload": f"replica batch ({args.workload}): N={n}, R={R} replicas, 200 nm, "
                                    f"phi=10%, d={a4.mat.d * 1e9:.2f} nm, 20 mT, {args.periods} periods",
                        "sar_W_per_g": res["sar"] / 1e3, "sar_se_W_per_g": res["sar_se"] / 1e3,
                        "field_error_vs_fp64": field_err},

@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
 
 // The special cases of k_update3 (field along or across the axis, K = 0, diagnostics)
 // out of line: kept apart, the role paths schedule as a small kernel (measured: inlining
-// it slowed config 2's update from 11.9 to 12.3 us).
+// it slowed the update of one N = 5000 assembly with three replicas from 11.9 to 12.3 us).
 __device__ __noinline__ double np_epilogue_rare(const SysDesc& s, int i, int64_t k, int cur,
                                                 double ax, double ay, double az) {
   return np_epilogue<false>(s, i, k, cur, ax, ay, az);

@@ -185,7 +185,7 @@ class Assembly:
         return int(self.pos.shape[0])
 
 
-def config1(seed_offset: int = 0) -> Assembly:
+def lysosome_n100(seed_offset: int = 0) -> Assembly:
     """N=100 in an 80 nm lysosome, d=12 nm, random placement and 3-D axes, 20 mT,
     100 kHz, 2000 steps, 3 periods with the last one kept (FP64 end to end)."""
     c = 1
@@ -197,7 +197,7 @@ def config1(seed_offset: int = 0) -> Assembly:
                     {"phi": volume_fraction(n, R, d)})
 
 
-def config2(mu0Hmax: float = 0.02, n_periods: int = 5) -> Assembly:
+def lysosome_n5000(mu0Hmax: float = 0.02, n_periods: int = 5) -> Assembly:
     """N=5000 in a 250 nm lysosome, d=12 nm (phi=6.9 %), random 3-D axes, 100 kHz,
     2000 steps per period, 5 periods with the first discarded."""
     c = 2
@@ -208,7 +208,7 @@ def config2(mu0Hmax: float = 0.02, n_periods: int = 5) -> Assembly:
     return Assembly(pos, ax, mat, R, 3000 + c, {"phi": volume_fraction(n, R, d)})
 
 
-def config3_params(count: int = 256, seed: int = 1003):
+def uneven_batch_params(count: int = 256, seed: int = 1003):
     """Draws of the uneven batch: radius U(100,250) nm, phi U(1,20) %, d U(10,16) nm,
     Keff U(0.8,2.0)e4, mu0Hmax U(5,40) mT, N = round(phi (2R/d)^3) kept when
     200 <= N <= 8000."""
@@ -226,9 +226,9 @@ def config3_params(count: int = 256, seed: int = 1003):
     return out
 
 
-def config3(count: int = 256, n_periods: int = 3) -> list[Assembly]:
+def uneven_batch(count: int = 256, n_periods: int = 3) -> list[Assembly]:
     out = []
-    for a, p in enumerate(config3_params(count)):
+    for a, p in enumerate(uneven_batch_params(count)):
         pos = place_random(p["n"], p["R"], p["d"], 100000 + a)
         ax = axes_random_3d(p["n"], 200000 + a)
         mat = Material(d=p["d"], Keff=p["K"], mu0Hmax=p["H"], n_periods=n_periods,
@@ -237,7 +237,7 @@ def config3(count: int = 256, n_periods: int = 3) -> list[Assembly]:
     return out
 
 
-def config4_geometry():
+def replica_batch_geometry():
     """N=4096 in a 200 nm lysosome at phi=10 %: d = 2R (phi/N)^(1/3) = 11.60 nm."""
     n, R, phi = 4096, 200e-9, 0.10
     d = 2 * R * (phi / n) ** (1.0 / 3.0)
@@ -245,11 +245,11 @@ def config4_geometry():
     return pos, d, R
 
 
-def config4(n_axes_sets: int = 512) -> Assembly:
+def replica_batch_n4096(n_axes_sets: int = 512) -> Assembly:
     """Replica-batched form: shared positions, one set of random 3-D axes per replica
     (the paper's averaging over axis orientations, Sec. III.1), 20 mT, 100 kHz,
     3 periods with the last kept."""
-    pos, d, R = config4_geometry()
+    pos, d, R = replica_batch_geometry()
     n = pos.shape[0]
     rng_seed = 2004
     axes = np.concatenate([axes_random_3d(n, rng_seed + 7919 * s) for s in range(n_axes_sets)])
@@ -257,7 +257,7 @@ def config4(n_axes_sets: int = 512) -> Assembly:
     return Assembly(pos, axes, mat, R, 3004, {"phi": 0.10, "n_axes_sets": n_axes_sets})
 
 
-def config5_requests(count: int = 1000, seed: int = 1005, rate_hz: float = 1.0):
+def request_stream(count: int = 1000, seed: int = 1005, rate_hz: float = 1.0):
     """Poisson arrivals of loop requests: N log-uniform in [100, 8000], radius
     U(80,300) nm, phi U(1,20) % (d derived), f log-uniform in [1e5, 1e6] Hz, mu0Hmax
     U(5,50) mT, periods U{3..10} with one discarded."""

@@ -67,16 +67,16 @@ def test_dhdip_pair_closed_form(ctx, lib, prec, tol):
 
 
 def test_dhdip_trajectory_and_amplitudes(ctx, lib):
-    """FP64 runs follow the oracle, so Eq. 6 per particle agrees to rounding: config 1
+    """FP64 runs follow the oracle, so Eq. 6 per particle agrees to rounding: the N = 100
     and three replicas at their own amplitudes."""
-    a1 = W.config1()
+    a1 = W.lysosome_n100()
     pk = kmc.Params.from_dict(a1.mat.as_dict())
     a = lib.Assembly(ctx, a1.pos, a1.axes, lib.params_from_material(a1.mat, lib.FP64))
     a.run(1, seed=a1.seed)
     a.sync()
     ref = kmc.simulate(a1.pos, a1.axes, pk, seed=a1.seed, stream=0)
     got = a.dhdip(0)
-    print(f"config 1 mean Delta-_Hdip {got.mean() * 1e3:.4f} mT (oracle {ref.dhdip_per_np.mean() * 1e3:.4f})")
+    print(f"N=100 mean Delta-_Hdip {got.mean() * 1e3:.4f} mT (oracle {ref.dhdip_per_np.mean() * 1e3:.4f})")
     assert np.abs(got - ref.dhdip_per_np).max() < 1e-9 * np.abs(ref.dhdip_per_np).max()
     a.close()
     n = 60

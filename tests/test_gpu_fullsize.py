@@ -1,10 +1,10 @@
 """Parity at full benchmark size, in the launch configuration the benchmarks time, on
 outputs the FP64 oracle computes directly:
 
-* config 2: one assembly of N = 5000 (250 nm lysosome, d = 12 nm), FP32 field, three
+* one assembly of N = 5000 (250 nm lysosome, d = 12 nm), FP32 field, three
   replicas at 10, 20 and 40 mT set as per-replica amplitudes. One step from a random
   snapshot at two step indices, every particle of every replica against the oracle.
-* config 4: N = 4096 at phi = 10 %, 512 replicas with one axis set each, BF16x3 matrix
+* N = 4096 at phi = 10 %, 512 replicas with one axis set each, BF16x3 matrix
   form. One step of all 512 replicas from a random snapshot; four sampled replicas
   against the oracle.
 
@@ -42,8 +42,8 @@ def _check_step(diag_r, m_gpu, m_new, info, field_tol, p_tol):
     return err, int(np.count_nonzero(dif))
 
 
-def test_config2_full_size_step(ctx, lib):
-    w2 = W.config2()
+def test_n5000_three_amplitudes_full_size_step(ctx, lib):
+    w2 = W.lysosome_n5000()
     amps = (0.010, 0.020, 0.040)
     a = lib.Assembly(ctx, w2.pos, w2.axes, lib.params_from_material(w2.mat, lib.FP32_FIELD))
     a.set_replica_fields(list(amps))
@@ -54,14 +54,14 @@ def test_config2_full_size_step(ctx, lib):
             pk = kmc.Params.from_dict(dict(w2.mat.as_dict(), mu0Hmax=h))
             m_new, info = kmc.step(w2.pos, w2.axes, m_in[r], k, pk, w2.seed, r)
             err, nd = _check_step(diag[r], a.moments(r), m_new, info, 1e-5, 1e-4)
-            print(f"config 2, k={k}, {h * 1e3:g} mT: field error {err:.2e}, "
+            print(f"N=5000, k={k}, {h * 1e3:g} mT: field error {err:.2e}, "
                   f"{nd} decisions differ, {int(info.jump.sum())} jumps")
     a.close()
 
 
-def test_config4_full_size_step_sampled_replicas(ctx, lib):
+def test_n4096_512_replicas_full_size_step(ctx, lib):
     R = 512
-    a4 = W.config4(n_axes_sets=R)
+    a4 = W.replica_batch_n4096(n_axes_sets=R)
     n = a4.n
     a = lib.Assembly(ctx, a4.pos, a4.axes, lib.params_from_material(a4.mat, lib.BF16X3_WM),
                      n_axes_sets=R)
@@ -73,6 +73,6 @@ def test_config4_full_size_step_sampled_replicas(ctx, lib):
         axes_r = a4.axes[r * n:(r + 1) * n]
         m_new, info = kmc.step(a4.pos, axes_r, m_in[r], k, pk, a4.seed, r)
         err, nd = _check_step(diag[r], a.moments(r), m_new, info, 1e-4, 1e-3)
-        print(f"config 4, replica {r}: field error {err:.2e}, {nd} decisions differ, "
+        print(f"N=4096 x 512, replica {r}: field error {err:.2e}, {nd} decisions differ, "
               f"{int(info.jump.sum())} jumps")
     a.close()

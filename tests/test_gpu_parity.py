@@ -132,9 +132,10 @@ def test_single_step_parity(ctx, lib, n, prec, nrep):
                 assert np.abs(m_gpu[same] - m_new[same]).max() < 1e-4
 
 
-def test_trajectory_config1_fp64(ctx, lib):
-    """Config 1 (N=100, FP64, 3 periods of 2000 steps, last kept): same trajectory."""
-    a_in = W.config1()
+def test_trajectory_n100_fp64(ctx, lib):
+    """N=100 in an 80 nm lysosome, FP64, 3 periods of 2000 steps, last kept: the same
+    trajectory as the oracle."""
+    a_in = W.lysosome_n100()
     mat = a_in.mat
     pg = lib.params_from_material(mat, lib.FP64)
     pk = kmc.Params.from_dict(mat.as_dict())
@@ -145,7 +146,7 @@ def test_trajectory_config1_fp64(ctx, lib):
     H, M = a.loop(0, 0)
     ref = kmc.simulate(a_in.pos, a_in.axes, pk, seed=a_in.seed, stream=0)
     m_gpu = a.moments(0)
-    print(f"config1: GPU area {res['area']:.9g}, oracle {ref.area:.9g}; jumps {ref.jumps}")
+    print(f"lysosome_n100: GPU area {res['area']:.9g}, oracle {ref.area:.9g}; jumps {ref.jumps}")
     assert np.abs(m_gpu - ref.m_final).max() < 1e-8
     assert np.abs(M - ref.M[0]).max() < 1e-6 * pk.Ms
     assert np.abs(H - ref.H).max() < 1e-15

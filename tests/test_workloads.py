@@ -40,12 +40,12 @@ def test_axes_are_unit_and_isotropic():
 
 
 def test_config_samplers():
-    c1 = W.config1()
+    c1 = W.lysosome_n100()
     assert c1.n == 100 and abs(c1.meta["phi"] - 0.0422) < 1e-3
-    ps = W.config3_params()
+    ps = W.uneven_batch_params()
     assert len(ps) == 256 and all(200 <= p["n"] <= 8000 for p in ps)
-    d4 = W.config4_geometry()[1]
+    d4 = W.replica_batch_geometry()[1]
     assert abs(d4 - 11.60e-9) < 0.01e-9
-    reqs = W.config5_requests(count=200)
+    reqs = W.request_stream(count=200)
     assert all(100 <= q["n"] <= 8000 and 3 <= q["P"] <= 10 for q in reqs)
     assert all(np.diff([q["t"] for q in reqs]) > 0)
