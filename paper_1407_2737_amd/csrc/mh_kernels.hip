@@ -192,29 +192,43 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
 // ---------------------------------------------------------------------------
 // Tiled form: two launches per step k.
 //
-// Pairs (target, e) for e = q, q + Q, ... < ce of one staged chunk, geometry shared by
-// the G replicas' moments; kGuard masks the pair j == i.
+// Pairs (target, q + it Q), it < ce / Q, of one staged chunk; with G > 1 the pair
+// geometry is shared by the G replicas' moments; kGuard masks the pair j == i. The trip
+// count is the same for every lane (ce is a multiple of Q and q < Q), so the loop runs
+// on a scalar counter, and a full chunk of at most 16 trips is unrolled whole, which
+// makes every LDS offset an immediate: no per-pair VALU work but the pair terms.
 template <typename T, int G, bool kGuard, int Q, int CH, typename P4>
-__device__ __forceinline__ void group_pairs_q(int q, int ce, T xi, T yi, T zi, const P4* spos,
-                                              const P4 (*smom)[CH], T* bx, T* by, T* bz) {
-#pragma unroll 2
-  for (int e = q; e < ce; e += Q) {
-    const P4 pj = spos[e];
-    const T dx = (T)pj.x - xi, dy = (T)pj.y - yi, dz = (T)pj.z - zi;
-    const T r2 = dx * dx + dy * dy + dz * dz;
-    T inv = rsqrt_dist(r2);
-    if constexpr (kGuard) inv = r2 > (T)0 ? inv : (T)0;
-    const T inv2 = inv * inv;
-    const T inv3 = inv2 * inv;
-    const T s3 = (T)3 * inv2;
+__device__ __forceinline__ void chunk_pairs(int q, int ce, T xi, T yi, T zi, const P4* spos,
+                                            const P4 (*smom)[CH], T* bx, T* by, T* bz) {
+  auto pair = [&](int e) {
+    if constexpr (G == 1) {
+      dip_pair<T, kGuard>(xi, yi, zi, spos[e], smom[0][e], bx[0], by[0], bz[0]);
+    } else {
+      const P4 pj = spos[e];
+      const T dx = (T)pj.x - xi, dy = (T)pj.y - yi, dz = (T)pj.z - zi;
+      const T r2 = dx * dx + dy * dy + dz * dz;
+      T inv = rsqrt_dist(r2);
+      if constexpr (kGuard) inv = r2 > (T)0 ? inv : (T)0;
+      const T inv2 = inv * inv;
+      const T inv3 = inv2 * inv;
+      const T s3 = (T)3 * inv2;
 #pragma unroll
-    for (int r = 0; r < G; ++r) {
-      const P4 mj = smom[r][e];
-      const T md = ((T)mj.x * dx + (T)mj.y * dy + (T)mj.z * dz) * s3;
-      bx[r] += inv3 * (md * dx - (T)mj.x);
-      by[r] += inv3 * (md * dy - (T)mj.y);
-      bz[r] += inv3 * (md * dz - (T)mj.z);
+      for (int r = 0; r < G; ++r) {
+        const P4 mj = smom[r][e];
+        const T md = ((T)mj.x * dx + (T)mj.y * dy + (T)mj.z * dz) * s3;
+        bx[r] += inv3 * (md * dx - (T)mj.x);
+        by[r] += inv3 * (md * dy - (T)mj.y);
+        bz[r] += inv3 * (md * dz - (T)mj.z);
+      }
     }
+  };
+  if (CH / Q <= 16 && ce == CH) {
+#pragma unroll
+    for (int it = 0; it < CH / Q; ++it) pair(q + it * Q);
+  } else {
+    const int nit = ce / Q;
+#pragma unroll 2
+    for (int it = 0; it < nit; ++it) pair(q + it * Q);
   }
 }
 
@@ -309,23 +323,10 @@ __global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ s
       const int ce = (cn + Q - 1) / Q * Q;  // streams stay in lockstep over padded entries
       // only the chunk holding this block's targets can contain j == i
       const bool self = (tl.y * TI < c0 + cn) && (tl.y * TI + TI > c0);
-      if (G == 1) {
-        if (self) {
-#pragma unroll 4
-          for (int e = q; e < ce; e += Q)
-            dip_pair<T, true>(xi, yi, zi, spos[e], smom[0][e], bx[0], by[0], bz[0]);
-        } else {
-#pragma unroll 4
-          for (int e = q; e < ce; e += Q)
-            dip_pair<T, false>(xi, yi, zi, spos[e], smom[0][e], bx[0], by[0], bz[0]);
-        }
-      } else {
-        // geometry once per pair, applied to the G replicas' moments
-        if (self)
-          group_pairs_q<T, G, true, Q, CH>(q, ce, xi, yi, zi, spos, smom, bx, by, bz);
-        else
-          group_pairs_q<T, G, false, Q, CH>(q, ce, xi, yi, zi, spos, smom, bx, by, bz);
-      }
+      if (self)
+        chunk_pairs<T, G, true, Q, CH>(q, ce, xi, yi, zi, spos, smom, bx, by, bz);
+      else
+        chunk_pairs<T, G, false, Q, CH>(q, ce, xi, yi, zi, spos, smom, bx, by, bz);
     }
   }
   __syncthreads();  // every read of the staged chunk is done before red overwrites it
