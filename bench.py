@@ -34,8 +34,9 @@ MOMENT_FLOPS = 18               # per replica: 5 for m.r, 1 scale, 4 per compone
 # WRITE_SIZE over the default workload (one period), each scaled by what the counter
 # reads for a 256 MiB elementwise copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).
 # Tied to the kernel as measured: k_field<float,16,3> with three source parts per tile
+# and the pair loop unrolled over full chunks
 # (profiles/k_field_n5000x3_fp32.md); None for kernels without such a measurement.
-TRAFFIC_BYTES = {"k_field<float,16,3>": (1343.44 * 2.000 + 1406.25 * 1.000) * 1024}
+TRAFFIC_BYTES = {"k_field<float,16,3>": (1412.94 * 2.000 + 1406.25 * 1.000) * 1024}
 
 
 def cpu_baseline(assemblies, budget_s=15.0):
