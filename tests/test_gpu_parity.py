@@ -132,6 +132,44 @@ def test_single_step_parity(ctx, lib, n, prec, nrep):
                 assert np.abs(m_gpu[same] - m_new[same]).max() < 1e-4
 
 
+@pytest.mark.parametrize("prec,nrep", [(1, 1), (1, 2), (1, 3), (1, 4), (0, 1)])
+def test_single_step_parity_wide_tiles(lib, tmp_path, prec, nrep):
+    """The 64-target field tiles (whose chunks are too long to unroll whole, so their
+    pair loop runs on a scalar trip counter) for one to four FP32 replicas sharing the
+    pair geometry, and in FP64, forced by a loaded shape table: one fused step against
+    the oracle at two step indices."""
+    n = 1500
+    R_l = 80e-9 * (n / 100) ** (1 / 3)
+    pos = W.place_random(n, R_l, 12e-9, 900 + n)
+    axes = W.axes_random_3d(n, 901 + n)
+    path = tmp_path / "wide.json"
+    path.write_text('[\n  {"fp64": %d, "n_max": 2048, "groups_max": 1, "tile_kind": 0, '
+                    '"blocks_per_cu": 3, "us_per_step": 1.0}\n]\n' % (1 if prec == 0 else 0))
+    c = lib.Context(0)
+    c.load_shapes(str(path))
+    pg, pk = _params(lib, prec)
+    a = lib.Assembly(c, pos, axes, pg)
+    seed = 777
+    m_in = np.stack([_rand_moments(n, 30 + r) for r in range(nrep)])
+    for k in (0, 1234):
+        diag = a.debug_steps(nrep, seed, k, k + 1, m_in.reshape(-1, 3))
+        for r in range(nrep):
+            m_new, info = kmc.step(pos, axes, m_in[r], k, pk, seed, r)
+            m_gpu = a.moments(r)
+            errB = np.linalg.norm(diag[r, :, :3] - info.B) / np.linalg.norm(info.B)
+            print(f"prec={prec} R={nrep} k={k} replica {r}: field error {errB:.2e}")
+            assert errB < (1e-13 if prec == 0 else 2e-6), errB
+            dif = (diag[r, :, 4] == 1.0) != info.jump
+            if prec == 0:
+                assert not dif.any()
+                assert np.abs(m_gpu - m_new).max() < 1e-10
+            else:
+                assert np.all((np.abs(info.u - info.P) < 1e-4)[dif])
+                assert np.abs(m_gpu[~dif] - m_new[~dif]).max() < 1e-4
+    a.close()
+    c.close()
+
+
 def test_trajectory_n100_fp64(ctx, lib):
     """N=100 in an 80 nm lysosome, FP64, 3 periods of 2000 steps, last kept: the same
     trajectory as the oracle."""
