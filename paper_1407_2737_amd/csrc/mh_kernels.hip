@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
     __syncthreads();
     if (k >= s.kept0 && !s.field_only) {
       const double tot = block_sum_res(mxsum, red);
-      if (tid == 0) s.recpart[k - s.kept0] = tot;
+      if (tid < kRecSlots) s.recpart[(k - s.kept0) * kRecSlots + tid] = tid == 0 ? tot : 0.0;
     }
   }
 }
@@ -373,7 +373,6 @@ template <bool kScan>
 __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ systems,
                                                 const int2* __restrict__ blocks,
                                                 const int64_t* __restrict__ kbase, int64_t koff) {
-  __shared__ double red[4];
   // the block's (system, particle block) is uniform: keep it in scalar registers, so the
   // descriptor is read with scalar loads and data loads are not chained behind it
   const int2 blv = blocks[blockIdx.x];
@@ -390,9 +389,12 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
     sum_parts(s, i, fx, fy, fz);  // partial sums of the source parts, fixed order
     mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz);
   }
-  if (k >= s.kept0 && !s.field_only) {
-    const double tot = block_sum_256(mx, red);
-    if (threadIdx.x == 0) s.recpart[(k - s.kept0) * s.ntiles + bl.y] = tot;
+  if (k >= s.kept0 && !s.field_only) {  // the four wave sums of the loop record
+    double v = mx;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0)
+      s.recpart[((k - s.kept0) * s.ntiles + bl.y) * kRecSlots + (threadIdx.x >> 6)] = v;
   }
 }
 
@@ -404,34 +406,36 @@ __device__ __noinline__ double np_epilogue_rare(const SysDesc& s, int i, int64_t
   return np_epilogue<false>(s, i, k, cur, ax, ay, az);
 }
 
-// Launches of at most this many 256-particle blocks use k_update3 (one block per CU).
+// Launches of at most this many 256-particle blocks use k_update3.
 constexpr int kUpdate3MaxBlocks = 256;
 
 // Per-particle update with the roots of the fall spread over three waves per particle
-// (exact extremum search). A block holds 256 particles and 768 threads in three roles
-// of four waves: role 0 finds the global minimum, role 1 t* and the saddle, role 2 t*
-// and the metastable minimum, for the same particles; the roles meet in LDS and role 0
-// finishes steps v-vii and writes the outputs. On a launch with fewer waves than SIMDs
-// the three chains run side by side, so a step waits for the longest of them instead of
-// their sum. Each piece is the one sw_fall runs, so the results are those of k_update.
+// (exact extremum search). Each 256-particle update block runs as four sub-blocks of 64
+// particles and three waves: role 0 finds the global minimum, role 1 t* and the saddle,
+// role 2 t* and the metastable minimum, for the same particles; the roles meet in LDS
+// and role 0 finishes steps v-vii and writes the outputs and its wave's loop-record
+// slot. On a launch with fewer waves than SIMDs the three chains run side by side, so a
+// step waits for the longest of them instead of their sum, and small sub-blocks spread
+// the chains over four times as many CUs, so fewer of them share a SIMD's issue. Each
+// piece is the one sw_fall runs, so the results are those of k_update.
 // Special cases (field along or across the axis, K = 0, diagnostics) run whole on role 0.
-__global__ __launch_bounds__(768) void k_update3(const SysDesc* __restrict__ systems,
+__global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ systems,
                                                  const int2* __restrict__ blocks,
                                                  const int64_t* __restrict__ kbase,
                                                  int64_t koff) {
-  __shared__ double red[12];
-  __shared__ double2 sh_r2a[256], sh_r2b[256];
-  __shared__ int sh_two[256];
-  // the block's (system, particle block) is uniform: keep it in scalar registers, so the
-  // descriptor is read with scalar loads and data loads are not chained behind it
-  const int2 blv = blocks[blockIdx.x];
+  __shared__ double2 sh_r2a[64], sh_r2b[64];
+  __shared__ int sh_two[64];
+  // the sub-block's (system, particle block) is uniform: keep it in scalar registers, so
+  // the descriptor is read with scalar loads and data loads are not chained behind it
+  const int2 blv = blocks[blockIdx.x >> 2];
   const int2 bl = make_int2(__builtin_amdgcn_readfirstlane(blv.x),
                             __builtin_amdgcn_readfirstlane(blv.y));
+  const int part = (int)(blockIdx.x & 3);  // sub-block = wave of the 256-particle block
   const SysDesc& s = systems[bl.x];
   const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;                      // uniform over the block
-  const int role = threadIdx.x >> 8, t = threadIdx.x & 255;
-  const int i = bl.y * 256 + t;
+  const int role = threadIdx.x >> 6, t = threadIdx.x & 63;
+  const int i = bl.y * 256 + part * 64 + t;
   const int cur = (int)(k & 1);
   const bool act = i < s.n;
   double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -487,14 +491,11 @@ __global__ __launch_bounds__(768) void k_update3(const SysDesc* __restrict__ sys
       mx = np_epilogue_rare(s, i, k, cur, fx, fy, fz);
     }
   }
-  if (k >= s.kept0 && !s.field_only) {  // uniform over the block
-    double v = role == 0 ? mx : 0.0;
+  if (role == 0 && k >= s.kept0 && !s.field_only) {  // uniform over the wave
+    double v = mx;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0)
-      s.recpart[(k - s.kept0) * s.ntiles + bl.y] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (t == 0) s.recpart[((k - s.kept0) * s.ntiles + bl.y) * kRecSlots + part] = v;
   }
 }
 
@@ -516,7 +517,10 @@ __global__ __launch_bounds__(256) void k_finalize_sys(const SysDesc* __restrict_
   const int rows = s.total_steps - s.kept0;
   for (int r = tid; r < rows; r += 256) {
     double v = 0.0;
-    for (int q = 0; q < s.ntiles; ++q) v += s.recpart[(int64_t)r * s.ntiles + q];
+    for (int q = 0; q < s.ntiles; ++q) {
+      const double* w = s.recpart + ((int64_t)r * s.ntiles + q) * kRecSlots;
+      v += (w[0] + w[1]) + (w[2] + w[3]);
+    }
     ro[r] = v;
   }
 }
@@ -578,7 +582,9 @@ __global__ __launch_bounds__(256) void k_master(const SysDesc* __restrict__ syst
     if (k >= s.kept0) {
       neumaier_add(sum, comp, s.Ms * Bext * (mx - mx_prev));
       const double t = block_sum_256(act ? mx : 0.0, red);
-      if (threadIdx.x == 0) s.recpart[(int64_t)(k - s.kept0) * s.ntiles + blockIdx.x] = t;
+      if (threadIdx.x < kRecSlots)
+        s.recpart[((int64_t)(k - s.kept0) * s.ntiles + blockIdx.x) * kRecSlots + threadIdx.x] =
+            threadIdx.x == 0 ? t : 0.0;
     }
     mx_prev = mx;
   }
@@ -665,7 +671,7 @@ __global__ void k_init(const SysDesc* __restrict__ systems) {
     s.area[s.n + i] = 0.0;
     if (s.dhdip) s.dhdip[i] = 0.0;
   }
-  const int64_t rows = (int64_t)(s.total_steps - s.kept0) * s.ntiles;
+  const int64_t rows = (int64_t)(s.total_steps - s.kept0) * s.ntiles * kRecSlots;
   for (int64_t r = i; r < rows; r += (int64_t)gridDim.x * blockDim.x) s.recpart[r] = 0.0;
 }
 
@@ -808,7 +814,8 @@ hipError_t launch_update(bool scan, const SysDesc* d_sys, const int2* d_blocks, 
     hipLaunchKernelGGL(k_update<true>, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase,
                        koff);
   else if (nblocks <= kUpdate3MaxBlocks)
-    hipLaunchKernelGGL(k_update3, dim3(nblocks), dim3(768), 0, st, d_sys, d_blocks, kbase, koff);
+    hipLaunchKernelGGL(k_update3, dim3(4 * nblocks), dim3(192), 0, st, d_sys, d_blocks, kbase,
+                       koff);
   else
     hipLaunchKernelGGL(k_update<false>, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase,
                        koff);

@@ -14,6 +14,12 @@ struct alignas(16) F4 {
   float x, y, z, w;
 };
 
+// Loop record partial sums per 256-particle update block: one per 64-lane wave, so that
+// an update block may also run as four sub-blocks. A row's value is the sum over blocks,
+// in block order, of (w0 + w1) + (w2 + w3); a kernel that forms a block's total itself
+// stores it in slot 0 and zeros in the others.
+constexpr int kRecSlots = 4;
+
 // Everything one (assembly, replica) system needs on the device.
 struct SysDesc {
   const D4* pos64;   // positions / d (reduced units), n entries
@@ -22,7 +28,7 @@ struct SysDesc {
   D4* m64;           // FP64 moments, buffer b at m64 + b * stride
   F4* m32;           // FP32 copy used by FP32 field sums, same layout
   double* area;      // per-particle area accumulators: [n] sums then [n] compensations
-  double* recpart;   // loop record partial sums [n_kept * S][ntiles]
+  double* recpart;   // loop record partial sums [n_kept * S][ntiles][kRecSlots]
   double* diag;      // optional per-particle diagnostics (8 doubles each) or null
   D4* field;         // reduced dipolar sums, nsplit partial sums per particle ([part][n])
   double* rec;       // loop record of the kept steps: sum_i m_x after each step

@@ -328,10 +328,8 @@ __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ s
     double v = mx;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0)
-      s.recpart[(k - s.kept0) * s.ntiles + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if ((threadIdx.x & 63) == 0)
+      s.recpart[((k - s.kept0) * s.ntiles + blockIdx.x) * kRecSlots + (threadIdx.x >> 6)] = v;
   }
 }
 
