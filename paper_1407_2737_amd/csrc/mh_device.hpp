@@ -732,11 +732,13 @@ __device__ NPResult np_update(const NPParams& p, double Bx, double By, double Bz
   return np_finish(p, w, sw, nx, ny, nz, seed, stream, i, k);
 }
 
-// Steps vi-vii and the new moment, from the working plane and the fall (K > 0).
-__device__ __forceinline__ NPResult np_finish(const NPParams& p, const Plane& w,
-                                              const SWState& sw, double nx, double ny,
-                                              double nz, uint64_t seed, uint64_t stream,
-                                              int64_t i, int64_t k) {
+// Steps vi-vii and the new moment, from the working plane and the fall (K > 0); draw()
+// gives the particle's uniform number of the step, called only where two minima exist
+// at T > 0.
+template <typename Draw>
+__device__ __forceinline__ NPResult np_finish_with(const NPParams& p, const Plane& w,
+                                                   const SWState& sw, double nx, double ny,
+                                                   double nz, Draw&& draw) {
   NPResult out;
   out.P = 0.0;
   out.jump = 0;
@@ -755,7 +757,7 @@ __device__ __forceinline__ NPResult np_finish(const NPParams& p, const Plane& w,
       const double xc = exp(-a_c), xo = exp(-a_o), sum = xc + xo;
       P = sum >= kSumMin ? (xc * rcp64(sum)) * (-expm1(-p.nu0dt * sum)) : 0.0;
     }
-    const double u = philox_uniform(seed, stream, i, k);
+    const double u = draw();
     out.P = P;
     if (u < P) {
       s = sw.s_o;
@@ -767,6 +769,14 @@ __device__ __forceinline__ NPResult np_finish(const NPParams& p, const Plane& w,
   out.my = c * ny + s * w.uy;
   out.mz = c * nz + s * w.uz;
   return out;
+}
+
+__device__ __forceinline__ NPResult np_finish(const NPParams& p, const Plane& w,
+                                              const SWState& sw, double nx, double ny,
+                                              double nz, uint64_t seed, uint64_t stream,
+                                              int64_t i, int64_t k) {
+  return np_finish_with(p, w, sw, nx, ny, nz,
+                        [&] { return philox_uniform(seed, stream, i, k); });
 }
 
 // Mean-magnetisation (master-equation) state of one non-interacting particle: two

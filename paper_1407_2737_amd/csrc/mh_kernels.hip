@@ -444,6 +444,7 @@ __global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ sys
   Plane w;
   SWArgs a;
   Dir d1{0.0, 0.0};
+  double u = 0.0;
   if (act) {
     for (int p = 0; p < s.nsplit; ++p) {  // partial sums of the source parts, fixed order
       const D4 f = s.field[(int64_t)p * s.n + i];
@@ -460,6 +461,8 @@ __global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ sys
       a = sw_args(w.hx, w.hy);
       if (role == 0) {
         d1 = sw_min1(a);
+        // the step's uniform number, drawn while roles 1 and 2 find their roots
+        if (s.np.thermal) u = philox_uniform(s.seed, s.stream, i, k);
       } else {
         const SWT tt = sw_tstar(a);
         if (role == 1) {
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ sys
       const Dir d2b = two ? Dir{sh_r2b[t].x, sh_r2b[t].y} : Dir{0.0, 0.0};
       const SWState sw = sw_finish(a, w.d0, d1, two, d2a, d2b);
       const NPResult r =
-          np_finish(s.np, w, sw, q.nn.x, q.nn.y, q.nn.z, s.seed, s.stream, i, k);
+          np_finish_with(s.np, w, sw, q.nn.x, q.nn.y, q.nn.z, [&] { return u; });
       mx = np_out(s, i, k, cur, q, r);
     } else {
       mx = np_epilogue_rare(s, i, k, cur, fx, fy, fz);
