@@ -455,9 +455,10 @@ void add_tiled(Plan& pl, int fp64, int kind, const std::vector<SysDesc>& reps, i
       const int gi = gidx(fp64, kind, gn);
       const int sidx = (int)pl.til[gi].size();
       for (int r = 0; r < gn; ++r) pl.til[gi].push_back(reps[mem[g0 + r]]);
+      // part-major: the last part of each tile, the shortest, is dispatched last
       const int n = reps[0].n;
-      for (int it = 0; it < (n + TI - 1) / TI; ++it)
-        for (int part = 0; part < reps[0].nsplit; ++part)
+      for (int part = 0; part < reps[0].nsplit; ++part)
+        for (int it = 0; it < (n + TI - 1) / TI; ++it)
           pl.tiles[gi].push_back(int4{sidx, it, gn, part});
     }
   }
