@@ -252,15 +252,18 @@ __global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ s
   constexpr int CH = G <= 3 ? 1024 : 512;          // sources per staged chunk
   constexpr int NPART = Q / 16;                    // first-level sums of 16 streams
   constexpr size_t kStage = sizeof(P4) * CH * (1 + G);
-  constexpr size_t kRed = sizeof(T) * 3 * G * Q * TI;
+  constexpr int TIP = TI + 1;  // stream rows padded: the 16-stream groups on distinct banks
+  constexpr size_t kRed = sizeof(T) * 3 * G * Q * TIP;
   constexpr size_t kPart = sizeof(double) * 3 * G * NPART * TI;
-  constexpr size_t kLds = kStage > kRed + kPart ? kStage : kRed + kPart;
-  static_assert(Q % 16 == 0 && kRed % sizeof(double) == 0, "stream layout");
+  constexpr size_t kRedEnd = (kRed + 7) / 8 * 8 + kPart;
+  constexpr size_t kLds = kStage > kRedEnd ? kStage : kRedEnd;
+  static_assert(Q % 16 == 0, "stream layout");
   __shared__ __align__(16) unsigned char lds[kLds];
   P4* spos = reinterpret_cast<P4*>(lds);                           // staged chunk
   P4 (*smom)[CH] = reinterpret_cast<P4 (*)[CH]>(lds + sizeof(P4) * CH);
-  T (*red)[G][Q][TI] = reinterpret_cast<T (*)[G][Q][TI]>(lds);     // after the last chunk
-  double (*part)[G][NPART][TI] = reinterpret_cast<double (*)[G][NPART][TI]>(lds + kRed);
+  T (*red)[G][Q][TIP] = reinterpret_cast<T (*)[G][Q][TIP]>(lds);   // after the last chunk
+  double (*part)[G][NPART][TI] =
+      reinterpret_cast<double (*)[G][NPART][TI]>(lds + (kRed + 7) / 8 * 8);
   const int4 tlv = tiles[blockIdx.x];  // (first system, i-tile, replicas, part), uniform
   const int4 tl = make_int4(__builtin_amdgcn_readfirstlane(tlv.x), __builtin_amdgcn_readfirstlane(tlv.y),
                             __builtin_amdgcn_readfirstlane(tlv.z), __builtin_amdgcn_readfirstlane(tlv.w));
