@@ -31,6 +31,20 @@ constexpr uint64_t kPhM1 = 0xCA5A826395121157ull;
 constexpr uint64_t kPhW0 = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kPhW1 = 0xBB67AE8584CAA73Bull;
 
+// Full 128-bit product of a 64-bit constant and x from four 32 x 32 -> 64 products,
+// each with its carry-in folded into one multiply-add (none can overflow 64 bits):
+// a x = ah xh 2^64 + (ah xl + al xh) 2^32 + al xl.
+template <uint64_t A>
+__device__ __forceinline__ void mul128(uint64_t x, uint64_t& lo, uint64_t& hi) {
+  constexpr uint32_t al = (uint32_t)A, ah = (uint32_t)(A >> 32);
+  const uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32);
+  const uint64_t p0 = (uint64_t)al * xl;
+  const uint64_t p1 = (uint64_t)al * xh + (p0 >> 32);
+  const uint64_t p2 = (uint64_t)ah * xl + (uint32_t)p1;
+  hi = (uint64_t)ah * xh + (p1 >> 32) + (p2 >> 32);
+  lo = (p2 << 32) | (uint32_t)p0;
+}
+
 __device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2,
                                               uint64_t& c3, uint64_t k0, uint64_t k1) {
 #pragma unroll
@@ -39,8 +53,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64
       k0 += kPhW0;
       k1 += kPhW1;
     }
-    const uint64_t lo0 = kPhM0 * c0, hi0 = __umul64hi(kPhM0, c0);
-    const uint64_t lo1 = kPhM1 * c2, hi1 = __umul64hi(kPhM1, c2);
+    uint64_t lo0, hi0, lo1, hi1;
+    mul128<kPhM0>(c0, lo0, hi0);
+    mul128<kPhM1>(c2, lo1, hi1);
     const uint64_t n0 = hi1 ^ c1 ^ k0;
     const uint64_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
