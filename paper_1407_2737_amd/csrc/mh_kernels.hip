@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
     __syncthreads();
     if (k >= s.kept0 && !s.field_only) {
       const double tot = block_sum_res(mxsum, red);
-      if (tid < kRecSlots) s.recpart[(k - s.kept0) * kRecSlots + tid] = tid == 0 ? tot : 0.0;
+      if (tid < s.rec_slots) s.recpart[(k - s.kept0) * s.rec_slots + tid] = tid == 0 ? tot : 0.0;
     }
   }
 }
@@ -376,6 +376,7 @@ template <bool kScan>
 __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ systems,
                                                 const int2* __restrict__ blocks,
                                                 const int64_t* __restrict__ kbase, int64_t koff) {
+  __shared__ double red[4];
   // the block's (system, particle block) is uniform: keep it in scalar registers, so the
   // descriptor is read with scalar loads and data loads are not chained behind it
   const int2 blv = blocks[blockIdx.x];
@@ -392,12 +393,18 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
     sum_parts(s, i, fx, fy, fz);  // partial sums of the source parts, fixed order
     mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz);
   }
-  if (k >= s.kept0 && !s.field_only) {  // the four wave sums of the loop record
+  if (k >= s.kept0 && !s.field_only) {  // the loop record: wave sums or their total
     double v = mx;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0)
-      s.recpart[((k - s.kept0) * s.ntiles + bl.y) * kRecSlots + (threadIdx.x >> 6)] = v;
+    double* rp = s.recpart + ((k - s.kept0) * s.ntiles + bl.y) * s.rec_slots;
+    if (s.rec_slots == kRecSlots) {
+      if ((threadIdx.x & 63) == 0) rp[threadIdx.x >> 6] = v;
+    } else {  // uniform over the block
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) rp[0] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
   }
 }
 
@@ -409,8 +416,8 @@ __device__ __noinline__ double np_epilogue_rare(const SysDesc& s, int i, int64_t
   return np_epilogue<false>(s, i, k, cur, ax, ay, az);
 }
 
-// Launches of at most this many 256-particle blocks use k_update3.
-constexpr int kUpdate3MaxBlocks = 256;
+// Launches of at most kUpdate3MaxBlocks 256-particle blocks use k_update3; every system
+// in them keeps one loop-record slot per wave (rec_slots_for).
 
 // Per-particle update with the roots of the fall spread over three waves per particle
 // (exact extremum search). Each 256-particle update block runs as four sub-blocks of 64
@@ -502,6 +509,7 @@ __global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ sys
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if (t == 0) s.recpart[((k - s.kept0) * s.ntiles + bl.y) * kRecSlots + part] = v;
+    // (rec_slots == kRecSlots here: the launch holds at most kUpdate3MaxBlocks blocks)
   }
 }
 
@@ -524,8 +532,8 @@ __global__ __launch_bounds__(256) void k_finalize_sys(const SysDesc* __restrict_
   for (int r = tid; r < rows; r += 256) {
     double v = 0.0;
     for (int q = 0; q < s.ntiles; ++q) {
-      const double* w = s.recpart + ((int64_t)r * s.ntiles + q) * kRecSlots;
-      v += (w[0] + w[1]) + (w[2] + w[3]);
+      const double* w = s.recpart + ((int64_t)r * s.ntiles + q) * s.rec_slots;
+      v += s.rec_slots == kRecSlots ? (w[0] + w[1]) + (w[2] + w[3]) : w[0];
     }
     ro[r] = v;
   }
@@ -588,8 +596,8 @@ __global__ __launch_bounds__(256) void k_master(const SysDesc* __restrict__ syst
     if (k >= s.kept0) {
       neumaier_add(sum, comp, s.Ms * Bext * (mx - mx_prev));
       const double t = block_sum_256(act ? mx : 0.0, red);
-      if (threadIdx.x < kRecSlots)
-        s.recpart[((int64_t)(k - s.kept0) * s.ntiles + blockIdx.x) * kRecSlots + threadIdx.x] =
+      if ((int)threadIdx.x < s.rec_slots)
+        s.recpart[((int64_t)(k - s.kept0) * s.ntiles + blockIdx.x) * s.rec_slots + threadIdx.x] =
             threadIdx.x == 0 ? t : 0.0;
     }
     mx_prev = mx;
@@ -677,7 +685,7 @@ __global__ void k_init(const SysDesc* __restrict__ systems) {
     s.area[s.n + i] = 0.0;
     if (s.dhdip) s.dhdip[i] = 0.0;
   }
-  const int64_t rows = (int64_t)(s.total_steps - s.kept0) * s.ntiles * kRecSlots;
+  const int64_t rows = (int64_t)(s.total_steps - s.kept0) * s.ntiles * s.rec_slots;
   for (int64_t r = i; r < rows; r += (int64_t)gridDim.x * blockDim.x) s.recpart[r] = 0.0;
 }
 

@@ -14,11 +14,18 @@ struct alignas(16) F4 {
   float x, y, z, w;
 };
 
-// Loop record partial sums per 256-particle update block: one per 64-lane wave, so that
-// an update block may also run as four sub-blocks. A row's value is the sum over blocks,
-// in block order, of (w0 + w1) + (w2 + w3); a kernel that forms a block's total itself
-// stores it in slot 0 and zeros in the others.
+// Loop record partial sums per 256-particle update block. A system that may run under
+// k_update3 (R x ntiles <= kUpdate3MaxBlocks update blocks, the launches of at most that
+// many use it) keeps one per 64-lane wave, as k_update3 runs each block as four
+// sub-blocks: a row's value is then the sum over blocks, in block order, of
+// (w0 + w1) + (w2 + w3), and a kernel that forms a block's total itself stores it in
+// slot 0 and zeros in the others. Larger systems keep the block total alone (rec_slots
+// = 1), the same value.
 constexpr int kRecSlots = 4;
+constexpr int kUpdate3MaxBlocks = 256;
+inline int rec_slots_for(int64_t R, int64_t ntiles) {
+  return R * ntiles <= kUpdate3MaxBlocks ? kRecSlots : 1;
+}
 
 // Everything one (assembly, replica) system needs on the device.
 struct SysDesc {
@@ -28,7 +35,7 @@ struct SysDesc {
   D4* m64;           // FP64 moments, buffer b at m64 + b * stride
   F4* m32;           // FP32 copy used by FP32 field sums, same layout
   double* area;      // per-particle area accumulators: [n] sums then [n] compensations
-  double* recpart;   // loop record partial sums [n_kept * S][ntiles][kRecSlots]
+  double* recpart;   // loop record partial sums [n_kept * S][ntiles][rec_slots]
   double* diag;      // optional per-particle diagnostics (8 doubles each) or null
   D4* field;         // reduced dipolar sums, nsplit partial sums per particle ([part][n])
   double* rec;       // loop record of the kept steps: sum_i m_x after each step
@@ -47,6 +54,7 @@ struct SysDesc {
   int32_t S, total_steps, kept0, static_field;
   int32_t field_only;  // diagnostics: write the dipolar field to diag, change nothing
   int32_t nsplit;      // source parts of the tiled field sum (partials summed by the update)
+  int32_t rec_slots;   // loop record partial sums per update block (1 or kRecSlots)
 };
 
 // Operands of the interaction-matrix product (see mh_wm.hip).

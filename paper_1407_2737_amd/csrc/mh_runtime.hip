@@ -153,6 +153,7 @@ struct mh_asm {
   int resident = 0;
   int tile_kind = 0;  // 0: 64 targets per block, 1: 16
   int nsplit = 1;     // source parts per field tile
+  int rec_slots = 1;  // loop record partial sums per update block (rec_slots_for)
   DevBuf m64, m32, area, recpart, rec, sys_area, stats, diag, tmp, field, dhdip;
   // interaction-matrix form (W generated in the product kernel): M^T hi/lo (Rp x Kp),
   // B^T partial sums (k splits x Rp x Mp)
@@ -311,7 +312,8 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   if (a->p.precision == MH_FP32_FIELD && (e = a->m32.ensure(sizeof(F4) * 2 * R * n))) return e;
   if ((e = a->area.ensure(sizeof(double) * 2 * R * n))) return e;
   if ((e = a->dhdip.ensure(sizeof(double) * R * n))) return e;
-  if ((e = a->recpart.ensure(sizeof(double) * R * rows * a->ntiles * kRecSlots + 8))) return e;
+  a->rec_slots = rec_slots_for(R, a->ntiles);
+  if ((e = a->recpart.ensure(sizeof(double) * R * rows * a->ntiles * a->rec_slots + 8))) return e;
   if ((e = a->rec.ensure(sizeof(double) * R * rows + 8))) return e;
   if ((e = a->sys_area.ensure(sizeof(double) * R))) return e;
   if ((e = a->stats.ensure(sizeof(double) * 4))) return e;
@@ -355,7 +357,8 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.m32 = a->p.precision == MH_FP32_FIELD ? a->m32.as<F4>() + r * n : nullptr;
   s.area = a->area.as<double>() + r * 2 * n;
   const int64_t rows = (int64_t)n_kept(p) * p.steps_per_period;
-  s.recpart = a->recpart.as<double>() + r * rows * a->ntiles * kRecSlots;
+  s.recpart = a->recpart.as<double>() + r * rows * a->ntiles * a->rec_slots;
+  s.rec_slots = a->rec_slots;
   s.rec = a->rec.as<double>() + r * rows;
   s.field = a->resident ? nullptr : a->field.as<D4>() + r * n * a->nsplit;
   // without interactions no dipolar sum is formed: no field tiles, and the update
@@ -725,7 +728,8 @@ int run_mean_loop(mh_asm* a, int64_t R, hipStream_t st) {
   a->resident = 0;
   a->nsplit = 1;
   a->ntiles = (int)((n + 255) / 256);
-  if ((e = a->recpart.ensure(sizeof(double) * R * rows * a->ntiles * kRecSlots + 8)) ||
+  a->rec_slots = rec_slots_for(R, a->ntiles);
+  if ((e = a->recpart.ensure(sizeof(double) * R * rows * a->ntiles * a->rec_slots + 8)) ||
       (e = a->rec.ensure(sizeof(double) * R * rows + 8)) ||
       (e = a->sys_area.ensure(sizeof(double) * R)) || (e = a->stats.ensure(sizeof(double) * 4)))
     return e;
@@ -1499,7 +1503,8 @@ struct SReq {
 size_t request_bytes(int64_t n, const mh_params& p, int64_t R, int64_t maxR) {
   const int64_t rows = (int64_t)(p.n_periods - p.n_discard) * p.steps_per_period;
   const int64_t nt = (n + 255) / 256;
-  size_t b = (size_t)R * n * (2 * 32 + 2 * 16 + 16 + 8 + 32) + (size_t)R * rows * (nt * kRecSlots + 1) * 8;
+  size_t b = (size_t)R * n * (2 * 32 + 2 * 16 + 16 + 8 + 32) +
+             (size_t)R * rows * (nt * rec_slots_for(R, nt) + 1) * 8;
   b += (size_t)n * (32 + 16 + 32) + (size_t)maxR * 8 + 4096;
   if (p.precision == MH_BF16X3_WM) {
     const int64_t rq = 8 * wm_tile_rows(), kq = wm_tile_k();

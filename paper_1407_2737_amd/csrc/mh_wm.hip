@@ -328,8 +328,14 @@ __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ s
     double v = mx;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0)
-      s.recpart[((k - s.kept0) * s.ntiles + blockIdx.x) * kRecSlots + (threadIdx.x >> 6)] = v;
+    double* rp = s.recpart + ((k - s.kept0) * s.ntiles + blockIdx.x) * s.rec_slots;
+    if (s.rec_slots == kRecSlots) {
+      if ((threadIdx.x & 63) == 0) rp[threadIdx.x >> 6] = v;
+    } else {  // uniform over the block
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) rp[0] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
   }
 }
 
