@@ -102,6 +102,7 @@ __device__ __forceinline__ double block_sum_256(double v, double* red) {
 // systems (N = 100: 16.0 -> 14.2 us per step) but, with the update on one thread per
 // particle, cost 23 % of the throughput of many systems at once.
 constexpr int kResThreads = 256;
+static_assert(kResThreads / 64 == kRecSlots, "one loop-record slot per resident wave");
 
 // Fixed-order sum of one double per thread over a kResThreads block: wave sums, then a
 // pairwise tree over the waves.
@@ -183,8 +184,15 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
     }
     __syncthreads();
     if (k >= s.kept0 && !s.field_only) {
-      const double tot = block_sum_res(mxsum, red);
-      if (tid < s.rec_slots) s.recpart[(k - s.kept0) * s.rec_slots + tid] = tid == 0 ? tot : 0.0;
+      if (s.rec_slots == kRecSlots) {  // one slot per wave: no block reduction, no barrier
+        double v = mxsum;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if ((tid & 63) == 0) s.recpart[(k - s.kept0) * kRecSlots + (tid >> 6)] = v;
+      } else {
+        const double tot = block_sum_res(mxsum, red);
+        if (tid == 0) s.recpart[k - s.kept0] = tot;
+      }
     }
   }
 }
