@@ -92,3 +92,34 @@ def test_update_forms_agree_across_the_launch_threshold(lib):
         assert np.array_equal(small.loop(1, 0)[1], alone[2])
         small.close()
         big.close()
+
+
+def test_loop_record_slots_agree(lib, tmp_path):
+    """An assembly with at most 256 update blocks keeps one loop-record partial sum per
+    wave (it may run under the three-role kernel); a larger one keeps one total per
+    block. The same replica's loop and area must be bitwise the same either way: one
+    replica of a 300-particle FP64 assembly (2 blocks) against the same replica among
+    200 (400 blocks), both with 16-target field tiles (a loaded shape table, so that
+    the field sums run in the same order)."""
+    ctx = lib.Context(0)
+    path = tmp_path / "shapes.json"
+    path.write_text('[\n'
+                    '  {"fp64": 1, "n_max": 512, "groups_max": 1, "tile_kind": 1, '
+                    '"blocks_per_cu": 3, "us_per_step": 1.0},\n'
+                    '  {"fp64": 1, "n_max": 512, "groups_max": 256, "tile_kind": 1, '
+                    '"blocks_per_cu": 3, "us_per_step": 1.0}\n]\n')
+    ctx.load_shapes(str(path))
+    kw = dict(Ms=4e5, Keff=1.3e4, d=12e-9, T=300.0, tau0=1e-10, rho=5200.0, f=1e5,
+              mu0Hmax=0.02, steps_per_period=100, n_periods=2, n_discard=1)
+    pos = W.place_random(300, 60e-9, 12e-9, 81)
+    axes = W.axes_random_3d(300, 82)
+    a = lib.Assembly(ctx, pos, axes, lib.Params.make(lib.FP64, **kw))
+    a.run(1, seed=9)
+    a.sync()
+    one = (a.replica_areas()[0], a.moments(0).copy(), a.loop(0, 0)[1].copy())
+    a.run(200, seed=9)
+    a.sync()
+    assert a.replica_areas()[0] == one[0]
+    assert np.array_equal(a.moments(0), one[1])
+    assert np.array_equal(a.loop(0, 0)[1], one[2])
+    a.close()
