@@ -14,7 +14,8 @@
 //               launch, positions and field-side moments resident in LDS;
 //   k_field +   two launches per step: the dipolar sums over (system, i-tile) blocks
 //   k_update    with sources staged through LDS, then one thread per particle for
-//               the per-particle update.
+//               the per-particle update (k_update3 for launches of few blocks: the
+//               roots of the fall on three waves per particle, same results).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
