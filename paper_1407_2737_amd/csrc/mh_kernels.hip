@@ -161,9 +161,20 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
       T bx = 0, by = 0, bz = 0;
       if (i < n) {
         const P4 pi = pos[i];
-        if (s.Bscale != 0.0)  // interactions on (uniform over the block)
-          for (int j = sub; j < n; j += P)
+        if (s.Bscale != 0.0) {  // interactions on (uniform over the block)
+          // two pairs per trip into separate sums, so that their LDS reads and FP64
+          // chains overlap (one workgroup per system: the step is latency-bound)
+          T cx = 0, cy = 0, cz = 0;
+          int j = sub;
+          for (; j + P < n; j += 2 * P) {
             dip_pair<T>((T)pi.x, (T)pi.y, (T)pi.z, pos[j], mc[j], bx, by, bz);
+            dip_pair<T>((T)pi.x, (T)pi.y, (T)pi.z, pos[j + P], mc[j + P], cx, cy, cz);
+          }
+          if (j < n) dip_pair<T>((T)pi.x, (T)pi.y, (T)pi.z, pos[j], mc[j], bx, by, bz);
+          bx += cx;
+          by += cy;
+          bz += cz;
+        }
       }
       for (int off = P >> 1; off > 0; off >>= 1) {
         bx += __shfl_xor(bx, off, 64);
