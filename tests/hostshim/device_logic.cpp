@@ -137,4 +137,12 @@ void dl_master(int64_t n, const double* ax, double Ms, double BK, double beta, d
   for (int64_t i = 0; i < n; ++i) a += sum[i] + comp[i];
   area_out[0] = a / ((double)n * (n_periods - n_discard));
 }
+
+// The 128-bit products of the two Philox multipliers (lo, hi words per input).
+void dl_mul128(int64_t n, const uint64_t* x, uint64_t* out) {
+  for (int64_t q = 0; q < n; ++q) {
+    mh::mul128<mh::kPhM0>(x[q], out[4 * q], out[4 * q + 1]);
+    mh::mul128<mh::kPhM1>(x[q], out[4 * q + 2], out[4 * q + 3]);
+  }
+}
 }

@@ -39,6 +39,8 @@ def dl():
     L.dl_master.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_double, C.c_double,
                             C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_int, C.c_int,
                             dp, dp, dp]
+    u64p2 = C.POINTER(C.c_uint64)
+    L.dl_mul128.argtypes = [C.c_int64, u64p2, u64p2]
     return L
 
 
@@ -221,3 +223,22 @@ def test_eq5_where_both_rates_underflow(dl):
     assert np.all(np.isfinite(Mg)) and np.isfinite(Ag[0])
     assert np.abs(Mg - M.ravel()).max() < 1e-9 * np.abs(M).max()
     assert abs(Ag[0] - A) < 1e-9 * abs(A)
+
+
+def test_mul128_is_the_exact_product(dl):
+    """The Philox rounds' 128-bit product (four 32 x 32 -> 64 multiply-adds with the
+    carries folded in) equals the exact integer product, for random words and the
+    edge cases 0, 1, 2^32 - 1, 2^32 and 2^64 - 1."""
+    rng = np.random.default_rng(11)
+    x = rng.integers(0, 2**63, size=2000, dtype=np.int64).astype(np.uint64) * np.uint64(2)
+    x[1::2] += np.uint64(1)
+    edge = np.array([0, 1, 2**32 - 1, 2**32, 2**64 - 1, 2**63, 2**63 - 1], dtype=np.uint64)
+    x = np.concatenate([edge, x])
+    out = np.zeros((len(x), 4), dtype=np.uint64)
+    p = C.POINTER(C.c_uint64)
+    dl.dl_mul128(len(x), x.ctypes.data_as(p), out.ctypes.data_as(p))
+    for q, xv in enumerate(x.tolist()):
+        for m, (lo, hi) in zip((0xD2E7470EE14C6C93, 0xCA5A826395121157),
+                               ((out[q, 0], out[q, 1]), (out[q, 2], out[q, 3]))):
+            prod = m * int(xv)
+            assert int(lo) == prod & (2**64 - 1) and int(hi) == prod >> 64, (q, xv)
