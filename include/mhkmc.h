@@ -213,6 +213,26 @@ int mh_get_moments(mh_asm* a, int64_t replica, double* m);
 int mh_debug_steps(mh_asm* a, int64_t n_replicas, uint64_t seed, int64_t k0, int64_t k1,
                    const double* m_in, double* diag);
 
+/* Allocation-free form of mh_debug_field, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ *   d_m  device pointer, n x 3 doubles (row-major): the moments, read during the call's
+ *        work on the stream.
+ *   d_B  device pointer, n x 3 doubles: receives the Eq. 1 field (T) summed exactly as
+ *        mh_debug_field sums it (same kernels, launch form and order: bitwise the same
+ *        result). Both buffers stay the caller's.
+ *   hip_stream  a hipStream_t, or NULL for the context's stream. The call only enqueues
+ *        kernels (no allocation, no copy from the host, no synchronisation); d_B holds the
+ *        field once the stream has reached it, so it may be captured into a HIP graph.
+ * Every intermediate (descriptor, tile lists, moment copies, partial sums) lives in one
+ * fixed 16 MiB device array per GPU, owned by the library for the life of the process
+ * and shared by all calls on that GPU: enough for about 100 000 particles under the
+ * built-in launch shapes. Calls that overlap on one GPU (other streams, other threads)
+ * race on it; serialise them. The assembly's run state and results are not touched.
+ * MH_EINVAL for a null pointer or an interaction-matrix (MH_BF16X3_WM) assembly,
+ * MH_EBUDGET when the evaluation needs more than the fixed array, MH_EDEVICE for a
+ * launch failure. */
+int mh_field_noalloc(mh_asm* a, const double* d_m, double* d_B, void* hip_stream);
+
 /* Raw Philox-4x64-10 blocks for explicit counters (n_blocks x 4 words in, out). */
 int mh_debug_philox(mh_ctx* ctx, uint64_t seed, uint64_t stream, int64_t n_blocks,
                     const uint64_t* ctr, uint64_t* out);

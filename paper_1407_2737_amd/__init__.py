@@ -29,7 +29,7 @@ SYMBOLS = [
     "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
     "mh_ctx_autotune", "mh_ctx_load_shapes", "mh_get_dhdip",
     "mh_get_local_concentration", "mh_create_assembly_sets", "mh_get_field_error",
-    "mh_debug_sw_mode",
+    "mh_debug_sw_mode", "mh_field_noalloc",
 ]
 
 
@@ -114,6 +114,7 @@ def _lib():
             "mh_debug_sw": ([vp, i64, dp, dp, dp, dp], C.c_int),
             "mh_debug_sw_mode": ([vp, i32, i64, dp, dp, dp, dp], C.c_int),
             "mh_debug_field": ([vp, dp, dp], C.c_int),
+            "mh_field_noalloc": ([vp, vp, vp, vp], C.c_int),
             "mh_strerror": ([C.c_int], C.c_char_p),
             "mh_ctx_set_timing": ([vp, C.c_int], C.c_int),
             "mh_ctx_get_timing": ([vp, i32, dp, C.POINTER(i64)], C.c_int),
@@ -327,6 +328,13 @@ class Assembly:
         out = np.empty((self.n, 3))
         _check(_lib().mh_debug_field(self._h, _dp(m), _dp(out)), "mh_debug_field")
         return out
+
+    def field_noalloc(self, d_m: int, d_B: int, stream: int | None = None) -> None:
+        """mh_field_noalloc: d_m, d_B are device addresses of n x 3 doubles; only
+        enqueues kernels on ``stream`` (None: the library's stream)."""
+        _check(_lib().mh_field_noalloc(self._h, C.c_void_p(d_m), C.c_void_p(d_B),
+                                       C.c_void_p(stream) if stream else None),
+               "mh_field_noalloc")
 
 
 class Server:

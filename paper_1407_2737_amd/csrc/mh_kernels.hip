@@ -756,6 +756,48 @@ __global__ void k_sw(const double* __restrict__ hx, const double* __restrict__ h
 }
 
 // ---------------------------------------------------------------------------
+// Plan of one Eq. 1 field evaluation in caller-provided device memory: the descriptor
+// (passed by value), the part-major field tile list and the update block list of the
+// single system, and the caller's moments (n x 3 doubles) as the buffer-0 moments of
+// the descriptor (FP64, and the FP32 copy when m32 is set). Written by kernels, so
+// the plan needs neither a host copy nor an allocation.
+// ---------------------------------------------------------------------------
+__global__ void k_field_plan(SysDesc s, SysDesc* __restrict__ d_desc, int4* __restrict__ tiles,
+                             int tiles_per_part, int nsplit, int2* __restrict__ ublocks,
+                             int nublocks, const double* __restrict__ m_in) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *d_desc = s;
+  if (i < tiles_per_part * nsplit) tiles[i] = make_int4(0, i % tiles_per_part, 1, i / tiles_per_part);
+  if (i < nublocks) ublocks[i] = make_int2(0, i);
+  if (i < s.n) {
+    D4 m;
+    m.x = m_in[3 * i];
+    m.y = m_in[3 * i + 1];
+    m.z = m_in[3 * i + 2];
+    m.w = 0.0;
+    s.m64[i] = m;
+    if (s.m32) {
+      F4 f;
+      f.x = (float)m.x;
+      f.y = (float)m.y;
+      f.z = (float)m.z;
+      f.w = 0.f;
+      s.m32[i] = f;
+    }
+  }
+}
+
+// The three field components of each particle's diagnostics record (8 doubles) into
+// an n x 3 array.
+__global__ void k_field_out(const double* __restrict__ diag, double* __restrict__ B, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  B[3 * i] = diag[8 * i];
+  B[3 * i + 1] = diag[8 * i + 1];
+  B[3 * i + 2] = diag[8 * i + 2];
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_resident(bool fp64, bool scan, const SysDesc* d_sys, int nsys, int64_t k0,
@@ -853,6 +895,20 @@ hipError_t launch_update(bool scan, const SysDesc* d_sys, const int2* d_blocks, 
   else
     hipLaunchKernelGGL(k_update<false>, dim3(nblocks), dim3(256), 0, st, d_sys, d_blocks, kbase,
                        koff);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_plan(const SysDesc& s, SysDesc* d_desc, int4* tiles, int tiles_per_part,
+                             int nsplit, int2* ublocks, int nublocks, const double* m_in,
+                             hipStream_t st) {
+  const int cnt = max(max(s.n, tiles_per_part * nsplit), max(nublocks, 1));
+  hipLaunchKernelGGL(k_field_plan, dim3((cnt + 255) / 256), dim3(256), 0, st, s, d_desc, tiles,
+                     tiles_per_part, nsplit, ublocks, nublocks, m_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_out(const double* diag, double* B, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_field_out, dim3((n + 255) / 256), dim3(256), 0, st, diag, B, n);
   return hipGetLastError();
 }
 

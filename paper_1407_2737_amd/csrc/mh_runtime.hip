@@ -32,6 +32,10 @@ hipError_t launch_field(bool fp64, int kind, int G, const SysDesc* d_sys, const 
 hipError_t launch_update(bool scan, const SysDesc* d_sys, const int2* d_blocks, int nblocks,
                          const int64_t* kbase, int64_t koff, hipStream_t st);
 hipError_t launch_set_step(int64_t* kbase, int64_t v, bool add, hipStream_t st);
+hipError_t launch_field_plan(const SysDesc& s, SysDesc* d_desc, int4* tiles, int tiles_per_part,
+                             int nsplit, int2* ublocks, int nublocks, const double* m_in,
+                             hipStream_t st);
+hipError_t launch_field_out(const double* diag, double* B, int n, hipStream_t st);
 int wm_tile_rows();
 int wm_tile_reps();
 int wm_tile_k();
@@ -56,6 +60,14 @@ hipError_t launch_sw(const double* hx, const double* hy, const double* th0, doub
 }  // namespace mh
 
 using namespace mh;
+
+// Device scratch of the allocation-free field call (mh_field_noalloc): the plan, the
+// moment copies, the partial field sums and the per-particle records of one Eq. 1
+// evaluation. Every GPU the library runs on holds its own copy until the process ends.
+// In host code this name is only a stand-in for the symbol: kernels receive the
+// device address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -135,6 +147,7 @@ struct mh_ctx {
   std::vector<uint64_t> gkey;
   int use_graphs = 1;
   std::vector<ShapeEntry> shapes;  // autotuned shapes (empty: the built-in rule)
+  unsigned char* scratch = nullptr;  // this device's copy of `scratch` (device address)
 };
 
 struct mh_asm {
@@ -169,6 +182,22 @@ struct mh_asm {
 };
 
 namespace {
+
+// Device address of `scratch` on `device`, resolved once per device with that device
+// current (each GPU holds the array at its own address).
+std::mutex g_scratch_mu;
+std::unordered_map<int, unsigned char*> g_scratch_addr;
+int scratch_address(int device, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MH_EDEVICE;
+    it = g_scratch_addr.emplace(device, static_cast<unsigned char*>(p)).first;
+  }
+  *out = it->second;
+  return MH_OK;
+}
 
 inline int set_dev(mh_ctx* c) {
   return hipSetDevice(c->device) == hipSuccess ? MH_OK : MH_EDEVICE;
@@ -344,7 +373,8 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   return MH_OK;
 }
 
-SysDesc make_desc(const mh_asm* a, int64_t r) {
+// Material, field and protocol part of replica r's descriptor (no run buffers).
+SysDesc desc_physics(const mh_asm* a, int64_t r) {
   const mh_params& p = a->p;
   SysDesc s{};
   const int64_t n = a->n;
@@ -352,25 +382,6 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.pos64 = a->pos64.as<D4>() + pset * n;
   s.pos32 = a->pos32.as<F4>() + pset * n;
   s.axes = a->axes.as<D4>() + (r % a->n_axes_sets) * n;
-  s.m64 = a->m64.as<D4>() + r * n;
-  // FP32 moment copies exist only for the FP32 field form, which is their one reader
-  s.m32 = a->p.precision == MH_FP32_FIELD ? a->m32.as<F4>() + r * n : nullptr;
-  s.area = a->area.as<double>() + r * 2 * n;
-  const int64_t rows = (int64_t)n_kept(p) * p.steps_per_period;
-  s.recpart = a->recpart.as<double>() + r * rows * a->ntiles * a->rec_slots;
-  s.rec_slots = a->rec_slots;
-  s.rec = a->rec.as<double>() + r * rows;
-  s.field = a->resident ? nullptr : a->field.as<D4>() + r * n * a->nsplit;
-  // without interactions no dipolar sum is formed: no field tiles, and the update
-  // reads no partial sums (its dipolar part is exactly zero)
-  s.nsplit = a->p.interactions ? a->nsplit : 0;
-  s.sys_area = a->sys_area.as<double>() + r;
-  s.dhdip = a->dhdip.as<double>() + r * n;
-  s.diag = nullptr;
-  s.stride = a->R * n;
-  s.seed = a->seed;
-  s.stream = a->stream_base + (uint64_t)r;
-  s.k_origin = a->k_origin;
   const double V = 3.14159265358979323846 * p.d * p.d * p.d / 6.0;
   s.np.BK = p.Keff > 0 ? 2.0 * p.Keff / p.Ms : 0.0;
   s.np.BK_inv = p.Keff > 0 ? p.Ms / (2.0 * p.Keff) : 0.0;
@@ -392,12 +403,38 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   }
   s.Ms = p.Ms;
   s.n = (int32_t)n;
-  s.ntiles = a->ntiles;
   s.S = p.steps_per_period;
   s.total_steps = total_steps(p);
   s.kept0 = kept0(p);
   s.static_field = p.dt_override > 0 ? 1 : 0;
   s.field_only = 0;
+  return s;
+}
+
+SysDesc make_desc(const mh_asm* a, int64_t r) {
+  const mh_params& p = a->p;
+  SysDesc s = desc_physics(a, r);
+  const int64_t n = a->n;
+  s.m64 = a->m64.as<D4>() + r * n;
+  // FP32 moment copies exist only for the FP32 field form, which is their one reader
+  s.m32 = a->p.precision == MH_FP32_FIELD ? a->m32.as<F4>() + r * n : nullptr;
+  s.area = a->area.as<double>() + r * 2 * n;
+  const int64_t rows = (int64_t)n_kept(p) * p.steps_per_period;
+  s.recpart = a->recpart.as<double>() + r * rows * a->ntiles * a->rec_slots;
+  s.rec_slots = a->rec_slots;
+  s.rec = a->rec.as<double>() + r * rows;
+  s.field = a->resident ? nullptr : a->field.as<D4>() + r * n * a->nsplit;
+  // without interactions no dipolar sum is formed: no field tiles, and the update
+  // reads no partial sums (its dipolar part is exactly zero)
+  s.nsplit = a->p.interactions ? a->nsplit : 0;
+  s.sys_area = a->sys_area.as<double>() + r;
+  s.dhdip = a->dhdip.as<double>() + r * n;
+  s.diag = nullptr;
+  s.stride = a->R * n;
+  s.seed = a->seed;
+  s.stream = a->stream_base + (uint64_t)r;
+  s.k_origin = a->k_origin;
+  s.ntiles = a->ntiles;
   return s;
 }
 
@@ -1015,7 +1052,7 @@ int mh_ctx_create(int device, mh_ctx** out) {
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
-  if (set_resident_lds_limit() != hipSuccess) {
+  if (set_resident_lds_limit() != hipSuccess || scratch_address(device, &c->scratch)) {
     (void)hipStreamDestroy(c->stream);
     delete c;
     return MH_EDEVICE;
@@ -1411,6 +1448,62 @@ int mh_debug_field(mh_asm* a, const double* m, double* B_out) {
   for (int64_t q = 0; q < n; ++q)
     for (int c = 0; c < 3; ++c) B_out[3 * q + c] = d[8 * q + c];
   return MH_OK;
+}
+
+int mh_field_noalloc(mh_asm* a, const double* d_m, double* d_B, void* hip_stream) {
+  if (!a || !d_m || !d_B || a->p.precision == MH_BF16X3_WM) return MH_EINVAL;
+  mh_ctx* c = a->ctx;
+  if (!c->scratch) return MH_EDEVICE;
+  if (set_dev(c)) return MH_EDEVICE;
+  hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+  // the launch form mh_debug_field takes (one replica), so the sums run in its order
+  const int64_t n = a->n;
+  const bool fp64 = a->p.precision == MH_FP64;
+  const bool resident = wants_resident(a, 1);
+  const int kind = tile_kind_for(a, 1);
+  const int nsplit = resident ? 1 : nsplit_for(a, 1, kind);
+  const int ntiles = resident ? 1 : (int)((n + 255) / 256);
+  const int tpp = (int)((n + tile_width(kind) - 1) / tile_width(kind));
+  const int parts = a->p.interactions ? nsplit : 0;  // no field tiles without Eq. 1
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t o_desc = take(sizeof(SysDesc));
+  const size_t o_tiles = take(sizeof(int4) * (size_t)tpp * nsplit);
+  const size_t o_ub = take(sizeof(int2) * (size_t)ntiles);
+  const size_t o_m64 = take(sizeof(D4) * (size_t)n);
+  const size_t o_m32 = fp64 ? 0 : take(sizeof(F4) * (size_t)n);
+  const size_t o_field = resident ? 0 : take(sizeof(D4) * (size_t)n * nsplit);
+  const size_t o_diag = take(sizeof(double) * 8 * (size_t)n);
+  if (off > kNoAllocBytes) return MH_EBUDGET;
+  unsigned char* b = c->scratch;
+  SysDesc s = desc_physics(a, 0);
+  s.m64 = reinterpret_cast<D4*>(b + o_m64);
+  s.m32 = fp64 ? nullptr : reinterpret_cast<F4*>(b + o_m32);
+  s.field = resident ? nullptr : reinterpret_cast<D4*>(b + o_field);
+  s.diag = reinterpret_cast<double*>(b + o_diag);
+  s.nsplit = parts;
+  s.ntiles = ntiles;
+  s.rec_slots = rec_slots_for(1, ntiles);
+  s.stride = n;
+  s.field_only = 1;
+  SysDesc* d_desc = reinterpret_cast<SysDesc*>(b + o_desc);
+  int4* d_tiles = reinterpret_cast<int4*>(b + o_tiles);
+  int2* d_ub = reinterpret_cast<int2*>(b + o_ub);
+  const bool scan = a->p.extrema_mode == MH_EXTREMA_SCAN200;
+  if (launch_field_plan(s, d_desc, d_tiles, tpp, parts, d_ub, ntiles, d_m, st) != hipSuccess)
+    return MH_EDEVICE;
+  if (resident) {
+    if (launch_resident(fp64, scan, d_desc, 1, 0, 1, (int)n, st) != hipSuccess) return MH_EDEVICE;
+  } else if (launch_field(fp64, kind, 1, d_desc, d_tiles, tpp * parts, nullptr, 0, st) !=
+                 hipSuccess ||
+             launch_update(scan, d_desc, d_ub, ntiles, nullptr, 0, st) != hipSuccess) {
+    return MH_EDEVICE;
+  }
+  return launch_field_out(s.diag, d_B, (int)n, st) == hipSuccess ? MH_OK : MH_EDEVICE;
 }
 
 int mh_debug_philox(mh_ctx* c, uint64_t seed, uint64_t stream, int64_t n_blocks,
