@@ -105,7 +105,8 @@ int mh_ctx_destroy(mh_ctx* ctx);
  *   axes  n_axes_sets x n x 3 easy axes (normalised on input, zero rows rejected).
  *         Replica r uses axis set r mod n_axes_sets: one set shared by all replicas,
  *         or one per replica (averaging over axis orientations, Sec. III.1).
- * Initial moments are m_i = sign(n_i . x) n_i (sign(0) = +1). */
+ * Initial moments are m_i = sign(n_i . e_H) n_i (sign(0) = +1), e_H the unit field
+ * direction of params.field_dir. */
 int mh_create_assembly(mh_ctx* ctx, int64_t n, const double* pos, const double* axes,
                        int64_t n_axes_sets, const mh_params* params, mh_asm** out);
 
@@ -160,7 +161,7 @@ int mh_sync(mh_asm* a);
 
 /* Loop of one replica for kept period p (0 <= p < n_periods - n_discard):
  *   H_T[k]   applied mu0 H_k (T), k = 0 .. S-1
- *   M_Apm[k] M_S <m_x> after step k (A/m). */
+ *   M_Apm[k] M_S <m . e_H> after step k (A/m), the magnetisation along the field. */
 int mh_get_loop(mh_asm* a, int64_t replica, int32_t period, double* H_T, double* M_Apm);
 
 /* Loop area A (J/m^3: mean over particles and kept periods, averaged over replicas)
@@ -188,7 +189,7 @@ int mh_get_area_per_np(mh_asm* a, int64_t replica, double* area_per_np);
  * last run, MH_ENOTREADY before any run. */
 int mh_get_field_error(mh_asm* a, int64_t replica, double* rel_frobenius, double* max_over_rms);
 
-/* Eq. 6 per particle of one replica (n values, tesla): the x component of the dipolar
+/* Eq. 6 per particle of one replica (n values, tesla): the e_H component of the dipolar
  * field acting in the +mu0 Hmax step (k = 0 mod S, from that step's start-of-step
  * moments) minus that in the -mu0 Hmax step (k = S/2 mod S), averaged over the kept
  * periods; positive where the neighbours' field reinforces the applied one (Sec.
@@ -261,7 +262,7 @@ int mh_debug_field(mh_asm* a, const double* m, double* B_out);
  * arrive while others run start as soon as memory frees up and share the launches.
  * Each request runs rounds of up to 64 replicas (256 for the matrix form; replica r
  * uses Philox stream r) until
- * 2 SE <= max(target_rel_err |A|, 1e-3 * 2 Keff) with at least min_replicas, or
+ * 2 SE <= max(target_rel_err |A|, abs_err_floor) with at least min_replicas, or
  * max_replicas. A request's result is the same alone and in any mix.
  * ------------------------------------------------------------------------- */
 typedef struct mh_server mh_server;
@@ -274,6 +275,8 @@ typedef struct {
   mh_params params;
   uint64_t seed;
   double target_rel_err;  /* relative target for 2 SE of the area (e.g. 0.01) */
+  double abs_err_floor;   /* absolute floor for 2 SE of the area, J/m^3 (>= 0; 0: none):
+                             a request stops once 2 SE <= max(target_rel_err |A|, floor) */
   int64_t min_replicas, max_replicas;
 } mh_request;
 

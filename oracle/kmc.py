@@ -263,6 +263,19 @@ def simulate(pos, axes, p: Params, seed: int, stream: int = 0, n_steps: int | No
                       dhdip / max(n_kept, 1))
 
 
+def replica_stats(areas):
+    """Mean loop area over independent replicas and its standard error (Sec. III.1: a
+    result is the average over loops that differ only in their random draws and axes).
+    The replicas are independent, so the error of the mean is the sample standard
+    deviation (ddof = 1) over sqrt(R); one replica has no spread and gives 0."""
+    a = np.asarray(areas, dtype=np.float64)
+    R = a.shape[0]
+    mean = float(a.sum() / R)
+    if R < 2:
+        return mean, 0.0
+    return mean, float(np.sqrt(((a - mean) ** 2).sum() / (R - 1) / R))
+
+
 def sar_from_area(area, f, rho=5200.0):
     """Sec. III.2.a: SAR = A f / rho (W/kg) for an area A in J/m^3."""
     return area * f / rho

@@ -65,7 +65,8 @@ class Params(C.Structure):
 class Request(C.Structure):
     _fields_ = [("n", C.c_int64), ("pos", C.POINTER(C.c_double)), ("axes", C.POINTER(C.c_double)),
                 ("n_axes_sets", C.c_int64), ("params", Params), ("seed", C.c_uint64),
-                ("target_rel_err", C.c_double), ("min_replicas", C.c_int64),
+                ("target_rel_err", C.c_double), ("abs_err_floor", C.c_double),
+                ("min_replicas", C.c_int64),
                 ("max_replicas", C.c_int64)]
 
 
@@ -346,11 +347,12 @@ class Server:
                "mh_server_create")
 
     def submit(self, pos, axes, params: Params, seed: int, target_rel_err: float = 0.01,
-               min_replicas: int = 64, max_replicas: int = 8192, n_axes_sets: int = 1) -> int:
+               min_replicas: int = 64, max_replicas: int = 8192, n_axes_sets: int = 1,
+               abs_err_floor: float = 0.0) -> int:
         pos = _f64(pos)
         axes = _f64(axes, (n_axes_sets * pos.shape[0], 3))
         rq = Request(pos.shape[0], _dp(pos), _dp(axes), n_axes_sets, params, seed, target_rel_err,
-                     min_replicas, max_replicas)
+                     abs_err_floor, min_replicas, max_replicas)
         rid = C.c_uint64()
         _check(_lib().mh_server_submit(self._h, C.byref(rq), C.byref(rid)), "mh_server_submit")
         return rid.value

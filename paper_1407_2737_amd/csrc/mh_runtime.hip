@@ -136,6 +136,7 @@ struct mh_ctx {
   int n_cu = 256;
   DevBuf d_sys;
   PinBuf h_stage;
+  std::vector<unsigned char> staged;  // host image of the plan now in d_sys
   // optional per-launch timing of the step kernels (event pairs around each launch)
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -148,6 +149,10 @@ struct mh_ctx {
   int use_graphs = 1;
   std::vector<ShapeEntry> shapes;  // autotuned shapes (empty: the built-in rule)
   unsigned char* scratch = nullptr;  // this device's copy of `scratch` (device address)
+  // recorded after the last launch of a run that reads the plan in d_sys / d_kbase (or
+  // the captured graph): the next run, on any stream, waits for it before re-staging
+  hipEvent_t plan_done = nullptr;
+  bool plan_pending = false;
 };
 
 struct mh_asm {
@@ -201,6 +206,26 @@ int scratch_address(int device, unsigned char** out) {
 
 inline int set_dev(mh_ctx* c) {
   return hipSetDevice(c->device) == hipSuccess ? MH_OK : MH_EDEVICE;
+}
+
+// The context's plan staging (pinned stage, d_sys, d_kbase, graph) is shared by all its
+// runs, whatever stream they use: wait until the previous run no longer reads it.
+int wait_plan_free(mh_ctx* c) {
+  if (c->plan_pending && hipEventSynchronize(c->plan_done) != hipSuccess) return MH_EDEVICE;
+  c->plan_pending = false;
+  return MH_OK;
+}
+int mark_plan_busy(mh_ctx* c, hipStream_t st) {
+  if (!c->plan_done && hipEventCreateWithFlags(&c->plan_done, hipEventDisableTiming) != hipSuccess)
+    return MH_EDEVICE;
+  if (hipEventRecord(c->plan_done, st) != hipSuccess) return MH_EDEVICE;
+  c->plan_pending = true;
+  return MH_OK;
+}
+// An assembly's buffers may be reallocated by its next run: wait for its last one.
+int wait_asm_idle(mh_asm* a) {
+  if (a->ran && a->done && hipEventSynchronize(a->done) != hipSuccess) return MH_EDEVICE;
+  return MH_OK;
 }
 
 int total_steps(const mh_params& p) { return p.n_periods * p.steps_per_period; }
@@ -509,18 +534,23 @@ void add_tiled(Plan& pl, int fp64, int kind, const std::vector<SysDesc>& reps, i
   }
 }
 
-// Descriptor array for a group, uploaded through the pinned stage into the device
-// scratch at byte offset `off`. Returns the device pointer.
+// Host image of a run's plan: arrays placed at 256-byte aligned offsets of one blob,
+// uploaded to the context's d_sys in a single copy. An empty array has no place.
+constexpr size_t kNoPlace = ~(size_t)0;
+struct PlanBlob {
+  std::vector<unsigned char> h;
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    if (v.empty()) return kNoPlace;
+    const size_t off = (h.size() + 255) & ~(size_t)255;
+    h.resize(off + sizeof(T) * v.size(), 0);
+    std::memcpy(h.data() + off, v.data(), sizeof(T) * v.size());
+    return off;
+  }
+};
 template <typename T>
-T* stage_upload(mh_ctx* c, const std::vector<T>& v, size_t& off, hipStream_t st) {
-  if (v.empty()) return nullptr;
-  const size_t bytes = sizeof(T) * v.size();
-  off = (off + 255) & ~(size_t)255;
-  std::memcpy(static_cast<char*>(c->h_stage.p) + off, v.data(), bytes);
-  T* d = reinterpret_cast<T*>(c->d_sys.as<char>() + off);
-  (void)hipMemcpyAsync(d, static_cast<char*>(c->h_stage.p) + off, bytes, hipMemcpyHostToDevice, st);
-  off += bytes;
-  return d;
+T* blob_ptr(mh_ctx* c, size_t off) {
+  return off == kNoPlace ? nullptr : reinterpret_cast<T*>(c->d_sys.as<char>() + off);
 }
 
 // Event pair around a launch when timing is on; returns the index of the pair or -1.
@@ -567,7 +597,8 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   for (size_t q = 0; q < asms.size(); ++q) {
     mh_asm* a = asms[q];
     if (o.init) {
-      int e = prepare_run(a, Rs[q], seeds[q], wants_resident(a, Rs[q]), tile_kind_for(a, Rs[q]));
+      int e = wait_asm_idle(a);
+      if (!e) e = prepare_run(a, Rs[q], seeds[q], wants_resident(a, Rs[q]), tile_kind_for(a, Rs[q]));
       if (e) return e;
     }
     const bool fp64 = a->p.precision == MH_FP64;
@@ -596,35 +627,40 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     fin.push_back({a, {first, (int)all.size()}});
     if (a->p.precision == MH_BF16X3_WM) pl.wm.push_back(WMItem{a, first, wm_args(a)});
   }
-  // upload descriptors and tile lists
-  size_t bytes = 0;
-  auto add = [&](size_t b) { bytes = ((bytes + 255) & ~(size_t)255) + b; };
-  add(sizeof(SysDesc) * all.size());
-  add(sizeof(SysDesc) * pl.res64.size());
-  add(sizeof(SysDesc) * pl.res32.size());
+  // descriptors and tile lists, laid out as one blob; a plan identical to the one the
+  // context staged last (a server chunk of the same requests) is not uploaded again
+  PlanBlob blob;
+  const size_t o_all = blob.put(all), o_res64 = blob.put(pl.res64), o_res32 = blob.put(pl.res32);
+  size_t o_til[kGroups], o_tiles[kGroups];
   for (int gi = 0; gi < kGroups; ++gi) {
-    add(sizeof(SysDesc) * pl.til[gi].size());
-    add(sizeof(int4) * pl.tiles[gi].size());
+    o_til[gi] = blob.put(pl.til[gi]);
+    o_tiles[gi] = blob.put(pl.tiles[gi]);
   }
-  add(sizeof(SysDesc) * pl.upd.size());
-  add(sizeof(int2) * pl.ublocks.size());
-  bytes += 256;
-  if (hipStreamSynchronize(st) != hipSuccess) return MH_EDEVICE;  // stage reuse
+  const size_t o_upd = blob.put(pl.upd), o_ublocks = blob.put(pl.ublocks);
+  const size_t off = blob.h.size();
   int e;
-  if ((e = c->h_stage.ensure(bytes))) return e;
-  if ((e = c->d_sys.ensure(bytes))) return e;
-  size_t off = 0;
-  SysDesc* d_all = stage_upload(c, all, off, st);
-  SysDesc* d_res64 = stage_upload(c, pl.res64, off, st);
-  SysDesc* d_res32 = stage_upload(c, pl.res32, off, st);
+  if (!(c->d_sys.p && off <= c->d_sys.cap && blob.h == c->staged)) {
+    if ((e = wait_plan_free(c))) return e;  // stage reuse, whichever stream ran last
+    if (hipStreamSynchronize(st) != hipSuccess) return MH_EDEVICE;
+    if ((e = c->h_stage.ensure(off + 256)) || (e = c->d_sys.ensure(off + 256))) return e;
+    if (off) {
+      std::memcpy(c->h_stage.p, blob.h.data(), off);
+      if (hipMemcpyAsync(c->d_sys.p, c->h_stage.p, off, hipMemcpyHostToDevice, st) != hipSuccess)
+        return MH_EDEVICE;
+    }
+    c->staged.swap(blob.h);
+  }
+  SysDesc* d_all = blob_ptr<SysDesc>(c, o_all);
+  SysDesc* d_res64 = blob_ptr<SysDesc>(c, o_res64);
+  SysDesc* d_res32 = blob_ptr<SysDesc>(c, o_res32);
   SysDesc* d_til[kGroups];
   int4* d_tiles[kGroups];
   for (int gi = 0; gi < kGroups; ++gi) {
-    d_til[gi] = stage_upload(c, pl.til[gi], off, st);
-    d_tiles[gi] = stage_upload(c, pl.tiles[gi], off, st);
+    d_til[gi] = blob_ptr<SysDesc>(c, o_til[gi]);
+    d_tiles[gi] = blob_ptr<int4>(c, o_tiles[gi]);
   }
-  SysDesc* d_upd = stage_upload(c, pl.upd, off, st);
-  int2* d_ublocks = stage_upload(c, pl.ublocks, off, st);
+  SysDesc* d_upd = blob_ptr<SysDesc>(c, o_upd);
+  int2* d_ublocks = blob_ptr<int2>(c, o_ublocks);
   if (o.init) {
     if (launch_init(d_all, (int)all.size(), pl.nmax_all, st) != hipSuccess) return MH_EDEVICE;
   } else if (o.sync32) {
@@ -739,6 +775,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
         return MH_EDEVICE;
     }
   }
+  if ((e = mark_plan_busy(c, st))) return e;
   for (auto& f : fin) {
     mh_asm* a = f.first;
     if (!a->done && hipEventCreateWithFlags(&a->done, hipEventDisableTiming) != hipSuccess)
@@ -759,6 +796,7 @@ int run_mean_loop(mh_asm* a, int64_t R, hipStream_t st) {
   const int64_t n = a->n;
   const int64_t rows = (int64_t)n_kept(a->p) * a->p.steps_per_period;
   int e;
+  if ((e = wait_asm_idle(a))) return e;
   if ((e = a->m64.ensure(sizeof(D4) * 2 * R * n)) || (e = a->area.ensure(sizeof(double) * 2 * R * n)) ||
       (e = a->dhdip.ensure(sizeof(double) * R * n)))
     return e;
@@ -780,11 +818,17 @@ int run_mean_loop(mh_asm* a, int64_t R, hipStream_t st) {
     d.m32 = nullptr;
     all.push_back(d);
   }
-  if (hipStreamSynchronize(st) != hipSuccess) return MH_EDEVICE;  // stage reuse
-  if ((e = c->h_stage.ensure(sizeof(SysDesc) * R + 256)) || (e = c->d_sys.ensure(sizeof(SysDesc) * R + 256)))
-    return e;
-  size_t off = 0;
-  SysDesc* d_all = stage_upload(c, all, off, st);
+  if ((e = wait_plan_free(c))) return e;  // stage reuse, whichever stream ran last
+  if (hipStreamSynchronize(st) != hipSuccess) return MH_EDEVICE;
+  PlanBlob blob;
+  const size_t o_all = blob.put(all);
+  const size_t off = blob.h.size();
+  if ((e = c->h_stage.ensure(off + 256)) || (e = c->d_sys.ensure(off + 256))) return e;
+  std::memcpy(c->h_stage.p, blob.h.data(), off);
+  if (hipMemcpyAsync(c->d_sys.p, c->h_stage.p, off, hipMemcpyHostToDevice, st) != hipSuccess)
+    return MH_EDEVICE;
+  c->staged.swap(blob.h);
+  SysDesc* d_all = blob_ptr<SysDesc>(c, o_all);
   if (launch_init(d_all, (int)R, (int)n, st) != hipSuccess) return MH_EDEVICE;
   const int tq = timing_begin(c, st, 5);
   if (launch_master(d_all, (int)R, (int)n, st) != hipSuccess) return MH_EDEVICE;
@@ -792,6 +836,7 @@ int run_mean_loop(mh_asm* a, int64_t R, hipStream_t st) {
   if (launch_finalize(d_all, (int)R, st) != hipSuccess ||
       launch_finalize_asm(a->sys_area.as<double>(), (int)R, a->stats.as<double>(), st) != hipSuccess)
     return MH_EDEVICE;
+  if ((e = mark_plan_busy(c, st))) return e;
   if (!a->done && hipEventCreateWithFlags(&a->done, hipEventDisableTiming) != hipSuccess)
     return MH_EDEVICE;
   if (hipEventRecord(a->done, st) != hipSuccess) return MH_EDEVICE;
@@ -1065,6 +1110,8 @@ int mh_ctx_destroy(mh_ctx* c) {
   if (!c) return MH_EINVAL;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->plan_pending) (void)hipEventSynchronize(c->plan_done);
+  if (c->plan_done) (void)hipEventDestroy(c->plan_done);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   c->d_kbase.release();
   c->d_sys.release();
@@ -1568,7 +1615,7 @@ int mh_debug_sw_mode(mh_ctx* c, int32_t extrema_mode, int64_t n, const double* h
 // (requests at different points of their runs share the launches; each reads its own
 // local step = clock - origin). A request runs in rounds of up to 64 replicas on
 // consecutive Philox streams; after each round the replica areas are appended on the
-// device and reduced, and the request finishes once 2 SE <= max(target |A|, 1e-3 2K)
+// device and reduced, and the request finishes once 2 SE <= max(target |A|, floor)
 // with at least min_replicas, or at max_replicas. Its result depends only on its own
 // inputs: launch forms are chosen per assembly and every system has its own streams.
 // ===========================================================================
@@ -1585,6 +1632,7 @@ struct SReq {
   mh_asm* a = nullptr;
   uint64_t seed = 0;
   double target = 0.01;
+  double floor = 0.0;  // absolute floor of 2 SE (J/m^3)
   int64_t minR = 64, maxR = 8192, done_R = 0, round_R = 0;
   int state = 0;  // 0 queued, 1 running, 2 done
   int64_t end = 0;
@@ -1593,19 +1641,32 @@ struct SReq {
   mh_result res{};
 };
 
-size_t request_bytes(int64_t n, const mh_params& p, int64_t R, int64_t maxR) {
-  const int64_t rows = (int64_t)(p.n_periods - p.n_discard) * p.steps_per_period;
-  const int64_t nt = (n + 255) / 256;
-  size_t b = (size_t)R * n * (2 * 32 + 2 * 16 + 16 + 8 + 32) +
-             (size_t)R * rows * (nt * rec_slots_for(R, nt) + 1) * 8;
-  b += (size_t)n * (32 + 16 + 32) + (size_t)maxR * 8 + 4096;
-  if (p.precision == MH_BF16X3_WM) {
+// Device memory a request holds while admitted: its geometry and the buffers that
+// prepare_run allocates for rounds of R replicas, under the launch form (resident,
+// tile shape and source parts) its runs will take, plus the per-replica areas of up to
+// maxR replicas.
+size_t request_bytes(const mh_asm* a, int64_t R, int64_t maxR) {
+  const mh_params& p = a->p;
+  const int64_t n = a->n;
+  const bool resident = wants_resident(a, R);
+  const bool wm = p.precision == MH_BF16X3_WM;
+  const int64_t rows = (int64_t)n_kept(p) * p.steps_per_period;
+  const int64_t ntiles = resident ? 1 : (n + 255) / 256;
+  const int64_t nsplit = resident ? 1 : nsplit_for(a, R, tile_kind_for(a, R));
+  size_t b = (size_t)n * a->n_pos_sets * (sizeof(D4) + sizeof(F4)) +
+             (size_t)n * a->n_axes_sets * sizeof(D4);
+  b += (size_t)R * n * (2 * sizeof(D4) + 2 * sizeof(double) + sizeof(double));
+  if (p.precision == MH_FP32_FIELD) b += (size_t)R * n * 2 * sizeof(F4);
+  b += sizeof(double) * ((size_t)R * rows * ntiles * rec_slots_for(R, ntiles) + 8);
+  b += sizeof(double) * ((size_t)R * rows + 8) + sizeof(double) * (R + 4);
+  if (!resident && !wm) b += sizeof(D4) * (size_t)R * n * nsplit;
+  if (wm) {
     const int64_t rq = 8 * wm_tile_rows(), kq = wm_tile_k();
     const int64_t Mp = (3 * n + rq - 1) / rq * rq, Kp = (3 * n + kq - 1) / kq * kq;
     const int64_t Rp = (R + wm_tile_reps() - 1) / wm_tile_reps() * wm_tile_reps();
-    b += (size_t)Rp * Kp * 4 + (size_t)wm_ksplit() * Rp * Mp * 4;
+    b += 2 * sizeof(__bf16) * (size_t)Rp * Kp + sizeof(float) * (size_t)wm_ksplit() * Rp * Mp;
   }
-  return b;
+  return b + sizeof(double) * (size_t)maxR;
 }
 
 }  // namespace
@@ -1621,7 +1682,7 @@ struct mh_server {
   uint64_t next_id = 1;
   bool stop = false;
   int64_t clock = 0;
-  int chunk = 50;
+  int chunk = 100;  // steps per scheduling chunk: two replays of the 50-step graph
   int64_t round_size = 64;
   int error = 0;
   std::thread th;
@@ -1671,8 +1732,8 @@ int mh_server::finish_round(SReq* q, bool& done) {
       hipStreamSynchronize(st) != hipSuccess)
     return MH_EDEVICE;
   const mh_params& p = q->a->p;
-  const double floor = 1e-3 * 2.0 * p.Keff;
-  const bool conv = q->done_R >= q->minR && 2.0 * stt[1] <= std::max(q->target * std::fabs(stt[0]), floor);
+  const bool conv =
+      q->done_R >= q->minR && 2.0 * stt[1] <= std::max(q->target * std::fabs(stt[0]), q->floor);
   done = conv || q->done_R >= q->maxR;
   if (done) {
     q->res.area_Jm3 = stt[0];
@@ -1796,13 +1857,17 @@ int mh_server_submit(mh_server* s, const mh_request* rq, uint64_t* req_id) {
   if (rq->min_replicas < 1 || rq->max_replicas < rq->min_replicas || rq->max_replicas > (1 << 20) ||
       !(rq->target_rel_err > 0))
     return MH_EINVAL;
+  if (!std::isfinite(rq->abs_err_floor) || rq->abs_err_floor < 0) return MH_EINVAL;
   const int64_t rs = rq->params.precision == MH_BF16X3_WM ? 4 * s->round_size : s->round_size;
   const int64_t R = std::min<int64_t>(rs, rq->max_replicas);
-  const size_t bytes = request_bytes(rq->n, rq->params, R, rq->max_replicas);
-  if (bytes > s->budget) return MH_EBUDGET;
   mh_asm* a = nullptr;
   int e = mh_create_assembly(s->ctx, rq->n, rq->pos, rq->axes, rq->n_axes_sets, &rq->params, &a);
   if (e) return e;
+  const size_t bytes = request_bytes(a, R, rq->max_replicas);
+  if (bytes > s->budget) {
+    mh_destroy_assembly(a);
+    return MH_EBUDGET;
+  }
   SReq* q = new (std::nothrow) SReq();
   if (!q) {
     mh_destroy_assembly(a);
@@ -1811,6 +1876,7 @@ int mh_server_submit(mh_server* s, const mh_request* rq, uint64_t* req_id) {
   q->a = a;
   q->seed = rq->seed;
   q->target = rq->target_rel_err;
+  q->floor = rq->abs_err_floor;
   q->minR = rq->min_replicas;
   q->maxR = rq->max_replicas;
   q->bytes = bytes;

@@ -78,3 +78,25 @@ def test_budget_refusal(lib):
         srv.submit(pos, axes, p, seed=1)
     assert e.value.code == -7
     srv.close()
+
+
+def test_budget_counts_axis_sets_and_state(lib):
+    """Admission counts every buffer a request's runs allocate: here 64 axis sets of
+    5000 particles (10 MB) alone exceed an 8 MiB budget although the per-replica state
+    of a one-replica round fits; with one axis set the same request is admitted and
+    finishes."""
+    ctx = lib.Context(0)
+    n, d = 5000, 12e-9
+    pos = W.place_lattice_disorder(n, d / 2 * (n / 0.05) ** (1 / 3), d, 71)
+    kw = dict(Ms=4e5, Keff=1.3e4, d=d, T=300.0, tau0=1e-10, rho=5200.0, f=1e5, mu0Hmax=0.02,
+              steps_per_period=100, n_periods=2, n_discard=1)
+    p = lib.Params.make(lib.FP32_FIELD, **kw)
+    srv = lib.Server(ctx, 8 << 20)
+    with pytest.raises(lib.MHError) as e:
+        srv.submit(pos, W.axes_random_3d(64 * n, 72), p, seed=1, min_replicas=1, max_replicas=1,
+                   n_axes_sets=64)
+    assert e.value.code == -7
+    i = srv.submit(pos, W.axes_random_3d(n, 73), p, seed=1, min_replicas=1, max_replicas=1)
+    r = _wait(srv, [i])[i]
+    assert r["status"] == 0 and r["replicas"] == 1
+    srv.close()
