@@ -12,9 +12,15 @@ every part of the path: dipolar field, Stoner-Wohlfarth extrema, switching draw,
 accumulation, then the SAR reduction). value = NP.steps executed / wall time, with the
 inputs already resident in device memory.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-secondary]
 
-Prints one JSON line.
+Prints one JSON line. Its roofline entry is for the dominant kernel (the tiled field
+sum): algorithmic flops per launch (29 per pair and replica, Eq. 1) over the kernel's
+mean duration, which mh_time_kernels measures with HIP events on graph replays of the
+timed run's own plan. Unless --no-secondary, the line also carries "secondary" lines for
+the other single-GPU configurations, each timed in the same process: N=100 in FP64 (one
+resident launch per run), 256 uneven assemblies with autotuned shapes, and 512 replicas
+of N=4096 in the interaction-matrix form on MFMA.
 """
 import argparse
 import json
@@ -26,17 +32,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VECTOR = 157.3e12     # MI355X published FP32 vector peak, FLOP/s
-FLOPS_PER_PAIR = 30             # Eq. 1 pair term, one replica: GEOM_FLOPS + MOMENT_FLOPS
-GEOM_FLOPS = 12                 # shared pair geometry: 3 differences, 5 for r^2, rsqrt, r^-2, r^-3, 3 r^-2
-MOMENT_FLOPS = 18               # per replica: 5 for m.r, 1 scale, 4 per component x 3
+PEAK_FP64_VECTOR = 78.6e12      # MI355X published FP64 vector peak, FLOP/s
+PEAK_BF16_MFMA = 2.5e15         # MI355X dense BF16 matrix peak, FLOP/s
+FLOPS_PER_PAIR = 29             # Eq. 1 pair term per system (FMA = 2): 3 differences, 5 for
+                                # r^2, 2 for r^-3, 5 for m.r, 2 for the 3 (m.r)/r^2 factor,
+                                # 12 for the accumulation; the reciprocal square root aside
+GEOM_FLOPS = 12                 # executed: pair geometry once per replica group
+MOMENT_FLOPS = 18               # executed: moment part per replica
+ALG_BYTES_PER_NP = 48           # HBM bytes per particle and system per step of the plain
+                                # form: position, moment in, field out (16 B each)
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE over the default workload (one period), each scaled by what the counter
-# reads for a 256 MiB elementwise copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000).
-# Tied to the kernel as measured: k_field<float,16,3> with three source parts per tile
-# and the pair loop unrolled over full chunks
-# (profiles/k_field_n5000x3_fp32.md); None for kernels without such a measurement.
-TRAFFIC_BYTES = {"k_field<float,16,3>": (1412.94 * 2.000 + 1406.25 * 1.000) * 1024}
+# WRITE_SIZE over the default workload, each scaled by what the counter reads for a
+# 256 MiB elementwise copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000); tied to the kernel
+# as measured (profiles/k_field_n5000x3_fp32.md). None where no such measurement exists.
+TRAFFIC_BYTES = {"k_field<float,16,3>": (1413.19 * 2.000 + 703.13 * 1.000) * 1024}
 
 
 _POOL_ASM = None  # the workload the pooled oracle leg steps (set before the fork)
@@ -100,6 +110,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--periods", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="default workload only: skip the secondary lines (N=100, 256 uneven "
+                         "assemblies, 512-replica matrix form)")
     ap.add_argument("--no-tune", action="store_true", help="uneven256: built-in launch-shape rule")
     ap.add_argument("--workload", default="n5000",
                     choices=["n100", "n5000", "uneven256", "replicas512", "replicas512plain",
@@ -114,27 +127,44 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    import numpy as np  # noqa: F401
     import paper_1407_2737_amd as mh
     from paper_1407_2737_amd import workloads as W
 
-    if args.workload == "uneven256":
-        return bench_uneven256(args, mh, W)
-    if args.workload == "master":
-        return bench_master(args, mh, W)
-    if args.workload == "n100":
-        return bench_n100(args, mh, W)
-    if args.workload == "sweep":
-        return bench_sweep(args, mh, W)
-    if args.workload == "methods":
-        return bench_methods(args, mh, W)
-    if args.workload == "figs":
-        return bench_figs(args, mh, W)
-    if args.workload in ("served", "servedwm"):
-        return bench_served(args, mh, W)
-    if args.workload != "n5000":
-        return bench_replicas512(args, mh, W)
+    single = {"uneven256": bench_uneven256, "master": bench_master, "n100": bench_n100,
+              "sweep": bench_sweep, "methods": bench_methods, "figs": bench_figs,
+              "served": bench_served, "servedwm": bench_served,
+              "replicas512": bench_replicas512, "replicas512plain": bench_replicas512}
+    if args.workload in single:
+        line = single[args.workload](args, mh, W)
+        if line is not None:
+            print(json.dumps(line), flush=True)
+        return
+    line = bench_n5000(args, mh, W)
+    if not args.no_secondary:
+        # the other single-GPU benchmark configurations, each timed here on its own:
+        # a few complete runs after one warm-up run, kernel durations on the same plan
+        sec = argparse.Namespace(**vars(args))
+        sec.steps, sec.warmup, sec.periods = 2, 1, 3
+        line["secondary"] = [bench_n100(sec, mh, W), bench_uneven256(sec, mh, W),
+                             bench_replicas512(argparse.Namespace(**dict(vars(sec),
+                                               workload="replicas512")), mh, W)]
+    print(json.dumps(line), flush=True)
 
+
+def _roof(bound, alg, us, peak, unit, kernel, **extra):
+    """Roofline entry of one kernel: algorithmic work per launch over its duration."""
+    ach = alg / (us * 1e-6)
+    out = {"bound": bound, "achieved": ach / 1e12, "peak": peak / 1e12, "unit": unit,
+           "frac": ach / peak, "kernel": kernel, "avg_launch_us": us,
+           "work_per_launch": alg}
+    out.update(extra)
+    return out
+
+
+def bench_n5000(args, mh, W):
+    """The default workload: one 5000-particle lysosome at three amplitudes."""
+    import numpy as np
     amps = (0.010, 0.020, 0.040)
     w2 = W.lysosome_n5000(n_periods=args.periods)
     work = [w2] * len(amps)
@@ -158,30 +188,10 @@ def main():
     for _ in range(args.steps):
         res = one_run()
     t1 = time.perf_counter()
-    # kernel durations: the timed runs replay captured graphs, which cannot carry
-    # per-launch events; one more run of the same plan launches the same kernels one by
-    # one, each bracketed by HIP events on the library's stream
-    ctx.set_timing(True)
-    one_run()
-    ms_kernel, launches = ctx.get_timing(0)
-    ms_update, launches_u = ctx.get_timing(3)
-    ctx.set_timing(False)
     wall = t1 - t0
     np_steps = n_total * steps_per_run * args.steps
     value = np_steps / wall
-    avg_launch_s = ms_kernel / 1e3 / max(launches, 1)
-    pairs_per_launch = sum(w.n * (w.n - 1) for w in work)
-    # algorithmic work of the replica-batched sum: the pair geometry once per pair
-    # (GEOM_FLOPS) and the moment part once per pair and replica (MOMENT_FLOPS)
-    flops_per_launch = (GEOM_FLOPS * w2.n * (w2.n - 1)
-                        + MOMENT_FLOPS * pairs_per_launch)
-    achieved = flops_per_launch / avg_launch_s
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
-                "traffic": TRAFFIC_BYTES.get("k_field<float,16,3>"),
-                "kernel": "k_field<float,16,3>", "avg_launch_us": avg_launch_s * 1e6,
-                "launches": launches, "flops_per_launch": flops_per_launch,
-                "update_kernel_avg_us": ms_update * 1e3 / max(launches_u, 1)}
+    us_step = wall / (args.steps * steps_per_run) * 1e6
     # per-particle area against depth below the membrane, 1 - |r|/R (the output of this
     # workload): mean per-particle area of each amplitude in depth bins of the last run
     depth = 1.0 - np.linalg.norm(w2.pos, axis=1) / w2.radius
@@ -199,6 +209,22 @@ def main():
     field_err = {f"{h * 1e3:g} mT": asm.field_error(r)[0] for r, h in enumerate(amps)}
     analyses = {"dhdip_mT_vs_depth": dh_profile, "corr_dhdip_area": corr,
                 "phi20_vs_depth": [float(phi20[which == b].mean()) for b in range(len(edges) - 1)]}
+    # kernel durations on the timed run's plan: 50 steps of launches of one kind,
+    # replayed back to back from a graph (the update replay overwrites the run's state,
+    # so it comes after every result above has been read)
+    us_field = mh.time_kernels([asm], 0, 50, 40)
+    us_update = mh.time_kernels([asm], 3, 50, 40)
+    pairs = sum(w.n * (w.n - 1) for w in work)
+    alg_bytes = ALG_BYTES_PER_NP * n_total
+    traffic = TRAFFIC_BYTES.get("k_field<float,16,3>")
+    roofline = _roof("alu", FLOPS_PER_PAIR * pairs, us_field, PEAK_FP32_VECTOR, "TFLOP/s",
+                     "k_field<float,16,3>", traffic=traffic,
+                     traffic_over_algorithmic=traffic / alg_bytes if traffic else None,
+                     algorithmic_bytes_per_launch=alg_bytes,
+                     executed_flops_per_launch=GEOM_FLOPS * w2.n * (w2.n - 1) + MOMENT_FLOPS * pairs,
+                     update_us_per_step=us_update,
+                     kernels_over_step=(us_field + us_update) / us_step,
+                     timing="graph replay of 50 steps x 40 on the timed run's plan, HIP events")
     line = {
         "metric": "NP·steps/s (dipolar+kMC)",
         "value": value,
@@ -216,6 +242,7 @@ def main():
                                "random 3-D axes, 10/20/40 mT batched, 100 kHz, "
                                f"{args.periods} periods x 2000 steps",
                    "n_particles_total": n_total, "steps_per_run": steps_per_run,
+                   "us_per_time_step": us_step,
                    "sar_W_per_g": [r["sar"] / 1e3 for r in res],
                    "area_Jm3_vs_depth": {"depth_edges": edges,
                                          "count": [int((which == b).sum())
@@ -227,7 +254,7 @@ def main():
     }
     if cpu is not None:
         line["cpu_baseline"] = cpu
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def bench_n100(args, mh, W):
@@ -250,8 +277,15 @@ def bench_n100(args, mh, W):
             asm.sync()
         out[R] = (time.perf_counter() - t0) / args.steps
     sar = asm.sar()
+    # the whole run is one resident launch: its duration from one event pair
+    ctx.set_timing(True)
+    asm.run(1024, seed=a1.seed)
+    asm.sync()
+    ms_k, launches = ctx.get_timing(1)
+    ctx.set_timing(False)
+    us_launch = ms_k * 1e3 / max(launches, 1)
     flops = FLOPS_PER_PAIR * a1.n * (a1.n - 1) * 1024 * steps_per_run   # Eq. 1 pair terms
-    line = {"metric": "NP·steps/s (dipolar+kMC)", "value": a1.n * 1024 * steps_per_run / out[1024],
+    return {"metric": "NP·steps/s (dipolar+kMC)", "value": a1.n * 1024 * steps_per_run / out[1024],
             "unit": "NP·steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": out[1024] * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -259,10 +293,9 @@ def bench_n100(args, mh, W):
                                    "3 periods x 2000 steps, FP64, 1024 replicas",
                        "us_per_time_step_one_replica": out[1] / steps_per_run * 1e6,
                        "sar_W_per_g": sar["sar"] / 1e3, "sar_se_W_per_g": sar["sar_se"] / 1e3},
-            "roofline": {"bound": "alu", "achieved": flops / out[1024] / 1e12, "peak": 78.6,
-                         "unit": "TFLOP/s", "frac": flops / out[1024] / 78.6e12, "traffic": None,
-                         "kernel": "k_resident<double> (whole run, pair terms only)"}}
-    print(json.dumps(line), flush=True)
+            "roofline": _roof("alu", flops, us_launch, PEAK_FP64_VECTOR, "TFLOP/s",
+                              "k_resident<double> (whole run; pair terms only counted)",
+                              traffic=None)}
 
 
 def bench_methods(args, mh, W):
@@ -616,13 +649,13 @@ def bench_uneven256(args, mh, W):
     """Batched uneven assemblies: 256 lysosomes with R ~ U(100,250) nm, phi ~ U(1,20) %,
     d ~ U(10,16) nm, K ~ U(0.8,2)e4, Hmax ~ U(5,40) mT, N in [200, 8000], one replica
     each, FP32 field, run together."""
+    import numpy as np
     work = W.uneven_batch(count=args.assemblies, n_periods=args.periods)
     ctx = mh.Context(0)
     tune = None
     if not args.no_tune:
         # launch shapes from the autotuner: one representative N (the median) per
         # particle-count bucket present in the batch, one replica each
-        import numpy as np
         ns = np.array(sorted(w.n for w in work if w.n > 256))
         buckets = 2 ** np.ceil(np.log2(np.maximum(ns, 256)))
         sizes = [int(np.median(ns[buckets == b])) for b in np.unique(buckets)]
@@ -633,6 +666,7 @@ def bench_uneven256(args, mh, W):
             for w in work]
     seeds = [w.seed for w in work]
     npsteps = sum(w.n * w.mat.steps_per_period * w.mat.n_periods for w in work)
+    steps_per_run = max(w.mat.steps_per_period * w.mat.n_periods for w in work)
 
     def one_run():
         mh.run_batch(asms, [1] * len(asms), seeds)
@@ -646,44 +680,42 @@ def bench_uneven256(args, mh, W):
     for _ in range(args.steps):
         sars = one_run()
     t1 = time.perf_counter()
-    ctx.set_timing(True)
-    one_run()
-    ms_k, launches = ctx.get_timing(0)
-    ms_u, lu = ctx.get_timing(3)
-    ms_r, lr = ctx.get_timing(1)
-    ctx.set_timing(False)
     wall = t1 - t0
     value = npsteps * args.steps / wall
+    us_step = wall / (args.steps * steps_per_run) * 1e6
+    tiled = [a for a, w in zip(asms, work) if w.n > 256]
+    us_field = mh.time_kernels(tiled, 0, 50, 10)
+    us_update = mh.time_kernels(tiled, 3, 50, 10)
     pairs = sum(w.n * (w.n - 1) for w in work if w.n > 256)
-    avg = ms_k / 1e3 / max(launches, 1)
-    roof = {"bound": "alu", "achieved": FLOPS_PER_PAIR * pairs / avg / 1e12,
-            "peak": PEAK_FP32_VECTOR / 1e12, "unit": "TFLOP/s",
-            "frac": FLOPS_PER_PAIR * pairs / avg / PEAK_FP32_VECTOR, "traffic": None,
-            "kernel": "k_field<float>", "avg_launch_us": avg * 1e6, "launches": launches,
-            "update_kernel_avg_us": ms_u * 1e3 / max(lu, 1), "resident_ms": ms_r}
-    line = {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
+    return {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32 field / f64 barrier", "data": "synthetic",
             "config": {"workload": f"{len(work)} uneven assemblies, N {min(w.n for w in work)}"
                                    f"-{max(w.n for w in work)}, {args.periods} periods x 2000 steps",
                        "n_particles_total": sum(w.n for w in work),
+                       "us_per_time_step": us_step,
                        "sar_W_per_g_median": float(sorted(sars)[len(sars) // 2]) / 1e3,
                        "autotuned_shapes": tune},
-            "roofline": roof}
-    print(json.dumps(line), flush=True)
+            "roofline": _roof("alu", FLOPS_PER_PAIR * pairs, us_field, PEAK_FP32_VECTOR,
+                              "TFLOP/s", "k_field<float> (all field launches of one step)",
+                              traffic=None, update_us_per_step=us_update,
+                              kernels_over_step=(us_field + us_update) / us_step,
+                              timing="graph replay of 50 steps x 10 on the timed run's plan "
+                                     "(tiled members; the resident members run in one "
+                                     "launch beside them)")}
 
 
 def bench_replicas512(args, mh, W):
     """Replica-batched form: N=4096 in a 200 nm lysosome at phi=10 %, one axis set per
     replica, R replicas on independent Philox streams; W.M on MFMA (replicas512) or the plain
     FP32 N-body kernels on the same replicas (replicas512plain)."""
-    import numpy as np
     R = args.replicas
     a4 = W.replica_batch_n4096(n_axes_sets=R)
     a4.mat.n_periods = args.periods
     a4.mat.n_discard = min(a4.mat.n_discard, args.periods - 1)
-    prec = mh.BF16X3_WM if args.workload == "replicas512" else mh.FP32_FIELD
+    wm = args.workload == "replicas512"
+    prec = mh.BF16X3_WM if wm else mh.FP32_FIELD
     ctx = mh.Context(0)
     asm = mh.Assembly(ctx, a4.pos, a4.axes, mh.params_from_material(a4.mat, prec), n_axes_sets=R)
     steps_per_run = a4.mat.steps_per_period * a4.mat.n_periods
@@ -699,47 +731,39 @@ def bench_replicas512(args, mh, W):
     for _ in range(args.steps):
         res = one_run()
     t1 = time.perf_counter()
-    ctx.set_timing(True)
-    one_run()
-    kind = 2 if args.workload == "replicas512" else 0
-    ms_k, launches = ctx.get_timing(kind)
-    ms_u, lu = ctx.get_timing(4 if args.workload == "replicas512" else 3)
-    ctx.set_timing(False)
     wall = t1 - t0
     n = a4.n
     value = n * R * steps_per_run * args.steps / wall
-    avg = ms_k / 1e3 / max(launches, 1)
-    if args.workload == "replicas512":
-        alg = 2.0 * (3 * n) ** 2 * R          # one W.M product per step
-        roof = {"bound": "mfma", "achieved": alg / avg / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
-                "frac": alg / avg / 2.5e15, "traffic": None, "kernel": "k_wm_gemm",
-                "avg_launch_us": avg * 1e6, "launches": launches,
-                "mfma_utilisation_executed": 3 * alg / avg / 2.5e15,
-                "update_kernel_avg_us": ms_u * 1e3 / max(lu, 1)}
-    else:
-        groups = (R + 3) // 4           # replicas share the pair geometry four at a time
-        alg = GEOM_FLOPS * n * (n - 1) * groups + MOMENT_FLOPS * n * (n - 1) * R
-        roof = {"bound": "alu", "achieved": alg / avg / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                "unit": "TFLOP/s", "frac": alg / avg / PEAK_FP32_VECTOR, "traffic": None,
-                "kernel": "k_field<float>", "avg_launch_us": avg * 1e6, "launches": launches,
-                "update_kernel_avg_us": ms_u * 1e3 / max(lu, 1)}
+    us_step = wall / (args.steps * steps_per_run) * 1e6
     # field error of this form on replica 0's final moments, against the FP64 field
     # kernel (which the parity tests hold within 1e-13 of the FP64 oracle): relative
     # Frobenius norm and the largest per-particle error over the rms field
     rel, mx = asm.field_error(0)
     field_err = {"rel_frobenius": rel, "max_over_rms": mx}
-    line = {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
+    us_k = mh.time_kernels([asm], 2 if wm else 0, 20, 10)
+    us_u = mh.time_kernels([asm], 4 if wm else 3, 20, 10)
+    if wm:
+        alg = 2.0 * (3 * n) ** 2 * R          # one W.M product per step
+        roof = _roof("mfma", alg, us_k, PEAK_BF16_MFMA, "TFLOP/s", "k_wm_gemm", traffic=None,
+                     mfma_utilisation_executed=3 * alg / (us_k * 1e-6) / PEAK_BF16_MFMA,
+                     update_us_per_step=us_u, kernels_over_step=(us_k + us_u) / us_step)
+    else:
+        alg = FLOPS_PER_PAIR * n * (n - 1) * R
+        roof = _roof("alu", alg, us_k, PEAK_FP32_VECTOR, "TFLOP/s", "k_field<float>",
+                     traffic=None, update_us_per_step=us_u,
+                     kernels_over_step=(us_k + us_u) / us_step)
+    return {"metric": "NP·steps/s (dipolar+kMC)", "value": value, "unit": "NP·steps/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None,
-            "dtype": "bf16x3 mfma / f64 barrier" if args.workload == "replicas512" else "f32 field / f64 barrier",
+            "dtype": "bf16x3 mfma / f64 barrier" if wm else "f32 field / f64 barrier",
             "data": "synthetic",
             "config": {"workload": f"replica batch ({args.workload}): N={n}, R={R} replicas, 200 nm, "
                                    f"phi=10%, d={a4.mat.d * 1e9:.2f} nm, 20 mT, {args.periods} periods",
+                       "us_per_time_step": us_step,
                        "sar_W_per_g": res["sar"] / 1e3, "sar_se_W_per_g": res["sar_se"] / 1e3,
                        "field_error_vs_fp64": field_err},
             "roofline": roof}
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -328,6 +328,21 @@ int mh_ctx_load_shapes(mh_ctx* ctx, const char* json_path);
 int mh_ctx_set_timing(mh_ctx* ctx, int on);
 int mh_ctx_get_timing(mh_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
 
+/* Kernel durations for roofline reports, on the plan of the assemblies' last run (run
+ * together by mh_run_batch or one by mh_run_loops, same replicas; not server requests):
+ * the launches of one step of one kernel kind are captured `launches` times (local
+ * steps from the first kept step where the run has enough of them), replayed once to
+ * warm up and then `reps` times back to back between two HIP events on the context's
+ * stream. *us_per_step = mean time of one step's launches of that kind, gaps between
+ * back-to-back launches included. kind: 0 tiled dipolar-sum launches, 2 interaction-matrix
+ * product, 3 per-particle update of the tiled form, 4 update of the matrix form (the
+ * numbering of mh_ctx_get_timing). Kinds 0 and 2 write only the field scratch; kinds 3
+ * and 4 advance moments and accumulators, so the assemblies' results are undefined until
+ * their next run. Synchronous. MH_EINVAL for an assembly that has not run, a server
+ * request, a repeated assembly, launches outside [1, 1000] or reps outside [1, 100000]. */
+int mh_time_kernels(mh_asm* const* asms, int32_t count, int32_t kind, int32_t launches,
+                    int32_t reps, double* us_per_step);
+
 const char* mh_strerror(int code);
 
 #ifdef __cplusplus

@@ -29,7 +29,7 @@ SYMBOLS = [
     "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
     "mh_ctx_autotune", "mh_ctx_load_shapes", "mh_get_dhdip",
     "mh_get_local_concentration", "mh_create_assembly_sets", "mh_get_field_error",
-    "mh_debug_sw_mode", "mh_field_noalloc",
+    "mh_debug_sw_mode", "mh_field_noalloc", "mh_time_kernels",
 ]
 
 
@@ -97,6 +97,7 @@ def _lib():
             "mh_destroy_assembly": ([vp], C.c_int),
             "mh_run_loops": ([vp, i64, u64, vp], C.c_int),
             "mh_run_batch": ([C.POINTER(vp), i32, C.POINTER(i64), u64p, vp], C.c_int),
+            "mh_time_kernels": ([C.POINTER(vp), i32, i32, i32, i32, dp], C.c_int),
             "mh_sync": ([vp], C.c_int),
             "mh_get_loop": ([vp, i64, i32, dp, dp], C.c_int),
             "mh_get_sar": ([vp, dp, dp, dp, dp, dp], C.c_int),
@@ -376,6 +377,17 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def time_kernels(assemblies, kind: int, launches: int = 50, reps: int = 20) -> float:
+    """mh_time_kernels: mean microseconds of one step's launches of one kernel kind,
+    replayed back to back on the plan of the assemblies' last run (kind 0 field sums,
+    2 matrix product, 3 update, 4 matrix-form update; 3 and 4 overwrite the run's state)."""
+    k = len(assemblies)
+    hs = (C.c_void_p * k)(*[a._h.value for a in assemblies])
+    us = C.c_double()
+    _check(_lib().mh_time_kernels(hs, k, kind, launches, reps, C.byref(us)), "mh_time_kernels")
+    return us.value
 
 
 def run_batch(assemblies, n_replicas, seeds, stream=None):

@@ -382,12 +382,16 @@ __global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ s
         ay += part[1][r][pp][t];
         az += part[2][r][pp][t];
       }
-      D4 f;
-      f.x = ax;
-      f.y = ay;
-      f.z = az;
-      f.w = 0.0;
-      systems[tl.x + r].field[(int64_t)tl.w * n + ii] = f;
+      // the part's sum, FP32 for the FP32 field form (the update adds parts in FP64)
+      P4 f;
+      f.x = (T)ax;
+      f.y = (T)ay;
+      f.z = (T)az;
+      f.w = (T)0;
+      if constexpr (sizeof(T) == 4)
+        systems[tl.x + r].field32[(int64_t)tl.w * n + ii] = f;
+      else
+        systems[tl.x + r].field[(int64_t)tl.w * n + ii] = f;
     }
   }
 }
@@ -477,10 +481,17 @@ __global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ sys
   double u = 0.0;
   if (act) {
     for (int p = 0; p < s.nsplit; ++p) {  // partial sums of the source parts, fixed order
-      const D4 f = s.field[(int64_t)p * s.n + i];
-      fx += f.x;
-      fy += f.y;
-      fz += f.z;
+      if (s.field32) {
+        const F4 f = s.field32[(int64_t)p * s.n + i];
+        fx += (double)f.x;
+        fy += (double)f.y;
+        fz += (double)f.z;
+      } else {
+        const D4 f = s.field[(int64_t)p * s.n + i];
+        fx += f.x;
+        fy += f.y;
+        fz += f.z;
+      }
     }
     if (!s.field_only && s.np.aniso) {
       q = np_in(s, i, k, cur, fx, fy, fz);

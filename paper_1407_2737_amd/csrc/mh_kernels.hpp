@@ -38,6 +38,7 @@ struct SysDesc {
   double* recpart;   // loop record partial sums [n_kept * S][ntiles][rec_slots]
   double* diag;      // optional per-particle diagnostics (8 doubles each) or null
   D4* field;         // reduced dipolar sums, nsplit partial sums per particle ([part][n])
+  F4* field32;       // the same partial sums in FP32 (FP32 field form; field is then null)
   double* rec;       // loop record of the kept steps: sum_i m_x after each step
   double* sys_area;  // this system's loop area (J/m^3), written at the end of a run
   double* dhdip;     // per-particle Eq. 6 sums over kept periods (T), or null
@@ -114,33 +115,42 @@ __device__ __forceinline__ NPIn np_in(const SysDesc& s, int i, int64_t k, int cu
   return np_in(s, k, ax, ay, az, s.m64[(int64_t)cur * s.stride + i], s.axes[i]);
 }
 
-// Sum of the nsplit partial fields of particle i in part order. The loads of four parts
-// at a time are issued together (addresses of missing parts fall back to part 0 and
-// their terms are skipped), so a few parts cost one memory round trip, not one each.
+// Sum of the nsplit partial fields of particle i in part order, in FP64 (the parts are
+// FP64, or FP32 for the FP32 field form). The loads of four parts at a time are issued
+// together (addresses of missing parts fall back to part 0 and their terms are skipped),
+// so a few parts cost one memory round trip, not one each.
+template <typename P4>
+__device__ __forceinline__ void sum_parts_of(const P4* field, int nsplit, int64_t n, int i,
+                                             double& fx, double& fy, double& fz) {
+  fx = fy = fz = 0.0;
+  for (int p0 = 0; p0 < nsplit; p0 += 4) {
+    const P4* b = field + (int64_t)p0 * n + i;
+    const int m = nsplit - p0;
+    const P4 f0 = ldg(b);
+    const P4 f1 = ldg(b + (m > 1 ? n : 0));
+    const P4 f2 = ldg(b + (m > 2 ? 2 * n : 0));
+    const P4 f3 = ldg(b + (m > 3 ? 3 * n : 0));
+    fx += (double)f0.x;
+    fy += (double)f0.y;
+    fz += (double)f0.z;
+    fx = m > 1 ? fx + (double)f1.x : fx;
+    fy = m > 1 ? fy + (double)f1.y : fy;
+    fz = m > 1 ? fz + (double)f1.z : fz;
+    fx = m > 2 ? fx + (double)f2.x : fx;
+    fy = m > 2 ? fy + (double)f2.y : fy;
+    fz = m > 2 ? fz + (double)f2.z : fz;
+    fx = m > 3 ? fx + (double)f3.x : fx;
+    fy = m > 3 ? fy + (double)f3.y : fy;
+    fz = m > 3 ? fz + (double)f3.z : fz;
+  }
+}
+
 __device__ __forceinline__ void sum_parts(const SysDesc& s, int i, double& fx, double& fy,
                                           double& fz) {
-  fx = fy = fz = 0.0;
-  const int64_t n = s.n;
-  for (int p0 = 0; p0 < s.nsplit; p0 += 4) {
-    const D4* b = s.field + (int64_t)p0 * n + i;
-    const int m = s.nsplit - p0;
-    const D4 f0 = ldg(b);
-    const D4 f1 = ldg(b + (m > 1 ? n : 0));
-    const D4 f2 = ldg(b + (m > 2 ? 2 * n : 0));
-    const D4 f3 = ldg(b + (m > 3 ? 3 * n : 0));
-    fx += f0.x;
-    fy += f0.y;
-    fz += f0.z;
-    fx = m > 1 ? fx + f1.x : fx;
-    fy = m > 1 ? fy + f1.y : fy;
-    fz = m > 1 ? fz + f1.z : fz;
-    fx = m > 2 ? fx + f2.x : fx;
-    fy = m > 2 ? fy + f2.y : fy;
-    fz = m > 2 ? fz + f2.z : fz;
-    fx = m > 3 ? fx + f3.x : fx;
-    fy = m > 3 ? fy + f3.y : fy;
-    fz = m > 3 ? fz + f3.z : fz;
-  }
+  if (s.field32)
+    sum_parts_of(s.field32, s.nsplit, s.n, i, fx, fy, fz);
+  else
+    sum_parts_of(s.field, s.nsplit, s.n, i, fx, fy, fz);
 }
 
 // Eq. 6: the dipolar field along e_H in the +Hmax step (k = 0 mod S) minus that in the

@@ -137,6 +137,8 @@ struct mh_ctx {
   DevBuf d_sys;
   PinBuf h_stage;
   std::vector<unsigned char> staged;  // host image of the plan now in d_sys
+  std::vector<hipGraphExec_t> timing_graphs;  // graphs of mh_time_kernels, kept to the end
+  hipEvent_t tev[2] = {nullptr, nullptr};
   // optional per-launch timing of the step kernels (event pairs around each launch)
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -372,7 +374,9 @@ int prepare_run(mh_asm* a, int64_t R, uint64_t seed, bool resident, int tile_kin
   if ((e = a->sys_area.ensure(sizeof(double) * R))) return e;
   if ((e = a->stats.ensure(sizeof(double) * 4))) return e;
   const bool wm = a->p.precision == MH_BF16X3_WM;
-  if (!resident && !wm && (e = a->field.ensure(sizeof(D4) * R * n * a->nsplit))) return e;
+  // partial field sums: FP32 for the FP32 field form, FP64 otherwise
+  const size_t part_bytes = a->p.precision == MH_FP32_FIELD ? sizeof(F4) : sizeof(D4);
+  if (!resident && !wm && (e = a->field.ensure(part_bytes * R * n * a->nsplit))) return e;
   if (wm) {
     {
       const int64_t rows = 3 * n;
@@ -448,7 +452,9 @@ SysDesc make_desc(const mh_asm* a, int64_t r) {
   s.recpart = a->recpart.as<double>() + r * rows * a->ntiles * a->rec_slots;
   s.rec_slots = a->rec_slots;
   s.rec = a->rec.as<double>() + r * rows;
-  s.field = a->resident ? nullptr : a->field.as<D4>() + r * n * a->nsplit;
+  const bool f32 = a->p.precision == MH_FP32_FIELD;
+  s.field = a->resident || f32 ? nullptr : a->field.as<D4>() + r * n * a->nsplit;
+  s.field32 = a->resident || !f32 ? nullptr : a->field.as<F4>() + r * n * a->nsplit;
   // without interactions no dipolar sum is formed: no field tiles, and the update
   // reads no partial sums (its dipolar part is exactly zero)
   s.nsplit = a->p.interactions ? a->nsplit : 0;
@@ -580,7 +586,51 @@ struct RunOpts {
   bool finalize = true;
   bool field_only = false;
   double* diag = nullptr;    // device diag buffer base (per asm: R*n*8)
+  // launch timing instead of a run: kernels of one kind (0 field sums, 2 matrix product,
+  // 3 update, 4 matrix-form update) for local steps time_k0 .. + time_launches-1, replayed
+  // back to back from a captured graph; mean microseconds per step into *time_us
+  int time_kind = -1;
+  int time_launches = 0, time_reps = 0;
+  int64_t time_k0 = 0;  // first local step of the timed launches
+  double* time_us = nullptr;
 };
+
+// Mean duration of `unit` (the launches of one step of one kernel kind): L units for
+// local steps kstart .. kstart+L-1 are captured once into a graph, replayed once to warm up, then
+// `reps` times between two events on the stream. The graph is kept until the context is
+// destroyed, so timing creates no destroy/instantiate churn between runs.
+template <typename F>
+int time_graph(mh_ctx* c, hipStream_t st, int64_t kstart, int L, int reps, F&& unit, double* us) {
+  int e;
+  if ((e = c->d_kbase.ensure(sizeof(int64_t)))) return e;
+  int64_t* kb = c->d_kbase.as<int64_t>();
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return MH_EDEVICE;
+  int rc = MH_OK;
+  for (int j = 0; j < L && rc == MH_OK; ++j) rc = unit(kb, j);
+  if (hipStreamEndCapture(st, &g) != hipSuccess || rc != MH_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return MH_EDEVICE;
+  }
+  const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) return MH_EDEVICE;
+  c->timing_graphs.push_back(x);
+  if (!c->tev[0] && (hipEventCreate(&c->tev[0]) != hipSuccess || hipEventCreate(&c->tev[1]) != hipSuccess))
+    return MH_EDEVICE;
+  if (launch_set_step(kb, kstart, false, st) != hipSuccess || hipGraphLaunch(x, st) != hipSuccess ||
+      hipEventRecord(c->tev[0], st) != hipSuccess)
+    return MH_EDEVICE;
+  for (int q = 0; q < reps; ++q)
+    if (hipGraphLaunch(x, st) != hipSuccess) return MH_EDEVICE;
+  float ms = 0.f;
+  if (hipEventRecord(c->tev[1], st) != hipSuccess || hipEventSynchronize(c->tev[1]) != hipSuccess ||
+      hipEventElapsedTime(&ms, c->tev[0], c->tev[1]) != hipSuccess)
+    return MH_EDEVICE;
+  *us = (double)ms * 1e3 / ((double)L * reps);
+  return MH_OK;
+}
 
 int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
                 const std::vector<uint64_t>& seeds, hipStream_t st, const RunOpts& o) {
@@ -673,6 +723,34 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       if (launch_wm_pack(d_all + it.first, (int)it.a->R, (int)it.a->n, it.g,
                          (int)((o.k0 - it.a->k_origin) & 1), st) != hipSuccess)
         return MH_EDEVICE;
+  if (o.time_kind >= 0) {
+    auto unit = [&](const int64_t* kb, int64_t koff) -> int {
+      hipError_t r = hipSuccess;
+      if (o.time_kind == 0) {
+        for (int f = 0; f < 2; ++f)
+          for (int kd = 0; kd < 2; ++kd)
+            for (int G = 1; G <= 4 && r == hipSuccess; ++G) {
+              const int gi = gidx(f, kd, G);
+              r = launch_field(f == 1, kd, G, d_til[gi], d_tiles[gi], (int)pl.tiles[gi].size(), kb,
+                               koff, st);
+            }
+      } else if (o.time_kind == 3) {
+        r = launch_update(pl.scan_upd, d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st);
+      } else {
+        for (auto& it : pl.wm) {
+          if (r != hipSuccess) break;
+          r = o.time_kind == 2
+                  ? launch_wm_gemm(it.g, st)
+                  : launch_wm_update(it.a->p.extrema_mode == MH_EXTREMA_SCAN200, d_all + it.first,
+                                     (int)it.a->R, (int)it.a->n, it.g, kb, koff, st);
+        }
+      }
+      return r == hipSuccess ? MH_OK : MH_EDEVICE;
+    };
+    if ((e = time_graph(c, st, o.time_k0, o.time_launches, o.time_reps, unit, o.time_us)))
+      return e;
+    return mark_plan_busy(c, st);
+  }
   const int64_t k0 = o.k0;
   const int64_t k1 = o.k1 < 0 ? pl.kmax : o.k1;
   const bool any_res = !pl.res64.empty() || !pl.res32.empty();
@@ -815,6 +893,7 @@ int run_mean_loop(mh_asm* a, int64_t R, hipStream_t st) {
   for (int64_t r = 0; r < R; ++r) {
     SysDesc d = make_desc(a, r);
     d.field = nullptr;
+    d.field32 = nullptr;
     d.m32 = nullptr;
     all.push_back(d);
   }
@@ -1113,6 +1192,9 @@ int mh_ctx_destroy(mh_ctx* c) {
   if (c->plan_pending) (void)hipEventSynchronize(c->plan_done);
   if (c->plan_done) (void)hipEventDestroy(c->plan_done);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  for (hipGraphExec_t x : c->timing_graphs) (void)hipGraphExecDestroy(x);
+  for (hipEvent_t ev : c->tev)
+    if (ev) (void)hipEventDestroy(ev);
   c->d_kbase.release();
   c->d_sys.release();
   c->h_stage.release();
@@ -1225,6 +1307,43 @@ int mh_run_batch(mh_asm* const* asms, int32_t count, const int64_t* n_replicas,
 int mh_run_loops(mh_asm* a, int64_t n_replicas, uint64_t seed, void* hip_stream) {
   mh_asm* arr[1] = {a};
   return mh_run_batch(arr, 1, &n_replicas, &seed, hip_stream);
+}
+
+int mh_time_kernels(mh_asm* const* asms, int32_t count, int32_t kind, int32_t launches,
+                    int32_t reps, double* us_per_step) {
+  if (!asms || count < 1 || !us_per_step || launches < 1 || launches > 1000 || reps < 1 ||
+      reps > 100000 || (kind != 0 && kind != 2 && kind != 3 && kind != 4))
+    return MH_EINVAL;
+  std::vector<mh_asm*> v;
+  std::vector<int64_t> R;
+  std::vector<uint64_t> S;
+  int64_t min_steps = INT64_MAX, min_kept0 = INT64_MAX;
+  for (int q = 0; q < count; ++q) {
+    mh_asm* a = asms[q];
+    if (!a || !a->ran || a->k_origin != 0 || a->R < 1) return MH_EINVAL;
+    for (int w = 0; w < q; ++w)
+      if (asms[w] == a) return MH_EINVAL;
+    if (wait_asm_idle(a)) return MH_EDEVICE;
+    v.push_back(a);
+    R.push_back(a->R);
+    S.push_back(a->seed);
+    min_steps = std::min<int64_t>(min_steps, total_steps(a->p));
+    min_kept0 = std::min<int64_t>(min_kept0, kept0(a->p));
+  }
+  RunOpts o;
+  o.init = false;
+  o.sync32 = false;
+  o.finalize = false;
+  o.time_kind = kind;
+  o.time_launches = (int)std::min<int64_t>(launches, min_steps);
+  // steps of the kept periods where there are enough of them (loop record and areas on)
+  o.time_k0 = std::max<int64_t>(0, std::min<int64_t>(min_kept0, min_steps - o.time_launches));
+  o.time_reps = reps;
+  o.time_us = us_per_step;
+  *us_per_step = 0.0;
+  const int e = run_systems(v, R, S, v[0]->ctx->stream, o);
+  if (e) return e;
+  return hipStreamSynchronize(v[0]->ctx->stream) == hipSuccess ? MH_OK : MH_EDEVICE;
 }
 
 int mh_sync(mh_asm* a) {
@@ -1523,14 +1642,16 @@ int mh_field_noalloc(mh_asm* a, const double* d_m, double* d_B, void* hip_stream
   const size_t o_ub = take(sizeof(int2) * (size_t)ntiles);
   const size_t o_m64 = take(sizeof(D4) * (size_t)n);
   const size_t o_m32 = fp64 ? 0 : take(sizeof(F4) * (size_t)n);
-  const size_t o_field = resident ? 0 : take(sizeof(D4) * (size_t)n * nsplit);
+  const size_t o_field =
+      resident ? 0 : take((fp64 ? sizeof(D4) : sizeof(F4)) * (size_t)n * nsplit);
   const size_t o_diag = take(sizeof(double) * 8 * (size_t)n);
   if (off > kNoAllocBytes) return MH_EBUDGET;
   unsigned char* b = c->scratch;
   SysDesc s = desc_physics(a, 0);
   s.m64 = reinterpret_cast<D4*>(b + o_m64);
   s.m32 = fp64 ? nullptr : reinterpret_cast<F4*>(b + o_m32);
-  s.field = resident ? nullptr : reinterpret_cast<D4*>(b + o_field);
+  s.field = resident || !fp64 ? nullptr : reinterpret_cast<D4*>(b + o_field);
+  s.field32 = resident || fp64 ? nullptr : reinterpret_cast<F4*>(b + o_field);
   s.diag = reinterpret_cast<double*>(b + o_diag);
   s.nsplit = parts;
   s.ntiles = ntiles;
@@ -1659,7 +1780,8 @@ size_t request_bytes(const mh_asm* a, int64_t R, int64_t maxR) {
   if (p.precision == MH_FP32_FIELD) b += (size_t)R * n * 2 * sizeof(F4);
   b += sizeof(double) * ((size_t)R * rows * ntiles * rec_slots_for(R, ntiles) + 8);
   b += sizeof(double) * ((size_t)R * rows + 8) + sizeof(double) * (R + 4);
-  if (!resident && !wm) b += sizeof(D4) * (size_t)R * n * nsplit;
+  if (!resident && !wm)
+    b += (p.precision == MH_FP32_FIELD ? sizeof(F4) : sizeof(D4)) * (size_t)R * n * nsplit;
   if (wm) {
     const int64_t rq = 8 * wm_tile_rows(), kq = wm_tile_k();
     const int64_t Mp = (3 * n + rq - 1) / rq * rq, Kp = (3 * n + kq - 1) / kq * kq;
