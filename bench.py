@@ -116,9 +116,16 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="uneven256: built-in launch-shape rule")
     ap.add_argument("--workload", default="n5000",
                     choices=["n100", "n5000", "uneven256", "replicas512", "replicas512plain",
-                             "served", "servedwm", "master", "sweep", "methods", "figs"])
-    ap.add_argument("--requests", type=int, default=24)
-    ap.add_argument("--max-replicas", type=int, default=64)
+                             "served", "master", "sweep", "methods", "figs"])
+    ap.add_argument("--requests", type=int, default=24, help="served: requests per arrival rate")
+    ap.add_argument("--sat-requests", type=int, default=8, help="served: saturation requests")
+    ap.add_argument("--rates", default="0.5,0.7,0.9", help="served: factors of the plain "
+                    "engine's saturated request rate")
+    ap.add_argument("--max-replicas", type=int, default=2048)
+    ap.add_argument("--engines", default="plain,matrix", help="served: plain and/or matrix")
+    ap.add_argument("--lambda0", type=float, default=0.0,
+                    help="served: the plain engine's saturated request rate (req/s) when it "
+                         "is not measured in this run")
     ap.add_argument("--assemblies", type=int, default=256)
     ap.add_argument("--replicas", type=int, default=512)
     args = ap.parse_args()
@@ -133,7 +140,7 @@ def main():
 
     single = {"uneven256": bench_uneven256, "master": bench_master, "n100": bench_n100,
               "sweep": bench_sweep, "methods": bench_methods, "figs": bench_figs,
-              "served": bench_served, "servedwm": bench_served,
+              "served": bench_served,
               "replicas512": bench_replicas512, "replicas512plain": bench_replicas512}
     if args.workload in single:
         line = single[args.workload](args, mh, W)
@@ -572,77 +579,106 @@ def bench_master(args, mh, W):
 
 
 def bench_served(args, mh, W):
-    """Serving: loop-simulation requests with N log-uniform in [100, 8000], radius
-    U(80,300) nm, phi U(1,20) %, f log-uniform in [1e5, 1e6] Hz, Hmax U(5,50) mT, 3-10
-    periods (one discarded). Phase 1 submits the first quarter at once to measure the
-    saturated request rate; phase 2 submits the rest as a Poisson stream at 0.7 of it.
-    Each request runs rounds of replicas until 2 SE <= max(1 % |A|, 1e-3 2K) or
-    --max-replicas."""
+    """Serving (continuous batching): loop-simulation requests with N log-uniform in
+    [100, 8000], radius U(80,300) nm, phi U(1,20) %, f log-uniform in [1e5, 1e6] Hz,
+    Hmax U(5,50) mT, 3-10 periods (one discarded), each run in rounds of replicas until
+    2 SE <= 1 % of its area (no absolute floor) or --max-replicas. Both engines serve the
+    same request stream: the plain FP32 N-body kernels and the interaction-matrix form on
+    MFMA. For each engine, the first --sat-requests requests are submitted at once to
+    measure its saturated request rate (they also warm it up); then, for each factor of
+    --rates, --requests further requests arrive as a Poisson stream at that factor of the
+    plain engine's saturated rate, on a fresh server. Reported per engine and rate:
+    kept loops/s, p50/p99 request latency, and the achieved 2 SE / area."""
     import numpy as np
-    prec = mh.BF16X3_WM if args.workload == "servedwm" else mh.FP32_FIELD
-    reqs = W.request_stream(count=args.requests, seed=1005, rate_hz=1.0)
-    inputs = []
+    rates = [float(x) for x in args.rates.split(",")]
+    n_sat, n_rate = args.sat_requests, args.requests
+    reqs = W.request_stream(count=n_sat + n_rate * len(rates), seed=1005, rate_hz=1.0)
+    geo = []
     for q in reqs:
-        Rl = q["R"]
-        pos = W.place_random(q["n"], Rl, q["d"], q["seed"])
+        pos = W.place_random(q["n"], q["R"], q["d"], q["seed"])
         axes = W.axes_random_3d(q["n"], q["seed"] + 1)
-        p = mh.Params.make(prec, Ms=4e5, Keff=1.3e4, d=q["d"], T=300.0, tau0=1e-10, rho=5200.0,
-                           f=q["f"], mu0Hmax=q["H"], steps_per_period=2000, n_periods=q["P"],
-                           n_discard=1)
-        inputs.append((pos, axes, p, q))
-    ctx = mh.Context(0)
-    srv = mh.Server(ctx, 200 << 30)
-    maxr = args.max_replicas if prec == mh.FP32_FIELD else max(args.max_replicas, 256)
+        geo.append((pos, axes, q))
 
-    def drain(ids, out):
-        while any(i not in out for i in ids):
+    def params(prec, q):
+        return mh.Params.make(prec, Ms=4e5, Keff=1.3e4, d=q["d"], T=300.0, tau0=1e-10,
+                              rho=5200.0, f=q["f"], mu0Hmax=q["H"], steps_per_period=2000,
+                              n_periods=q["P"], n_discard=1)
+
+    ctx = mh.Context(0)
+
+    def serve(prec, items, gaps, label):
+        srv = mh.Server(ctx, 200 << 30)
+        ids, t0 = [], time.perf_counter()
+        for (pos, axes, q), ta in zip(items, gaps):
+            while time.perf_counter() - t0 < ta:
+                time.sleep(0.0005)
+            ids.append(srv.submit(pos, axes, params(prec, q), seed=q["seed"], target_rel_err=0.01,
+                                  abs_err_floor=0.0, min_replicas=64,
+                                  max_replicas=args.max_replicas))
+        out = {}
+        while len(out) < len(ids):
             for i in ids:
                 if i not in out:
                     r = srv.poll(i)
                     if r is not None:
                         out[i] = r
+                        print(f"served {label}: {len(out)}/{len(ids)} done, {r['replicas']} "
+                              f"replicas, {(r['done_ns'] - r['submit_ns']) / 1e9:.2f} s",
+                              file=sys.stderr, flush=True)
             time.sleep(0.002)
+        srv.close()
+        res = [out[i] for i in ids]
+        first = min(r["submit_ns"] for r in res)
+        last = max(r["done_ns"] for r in res)
+        lat = np.array([(r["done_ns"] - r["submit_ns"]) / 1e9 for r in res])
+        rel = np.array([2 * r["area_se"] / max(abs(r["area_Jm3"]), 1e-300) for r in res])
+        loops = sum(r["loops"] for r in res)
+        npsteps = sum(q["n"] * 2000 * q["P"] * r["replicas"] for (_, _, q), r in zip(items, res))
+        span = (last - first) / 1e9
+        return {"requests": len(res), "seconds": span, "loops_per_s": loops / span,
+                "np_steps_per_s": npsteps / span,
+                "p50_latency_s": float(np.percentile(lat, 50)),
+                "p99_latency_s": float(np.percentile(lat, 99)),
+                "two_se_over_area_median": float(np.median(rel)),
+                "two_se_over_area_max": float(rel.max()),
+                "fraction_within_1pct": float(np.mean(rel <= 0.01 + 1e-12)),
+                "replicas_median": float(np.median([r["replicas"] for r in res])),
+                "replicas_max": int(max(r["replicas"] for r in res)),
+                "status_ok": all(r["status"] == 0 for r in res)}
 
-    n1 = max(1, len(inputs) // 4)
-    t0 = time.perf_counter()
-    ids1 = [srv.submit(x[0], x[1], x[2], seed=x[3]["seed"], target_rel_err=0.01,
-                       min_replicas=64, max_replicas=maxr) for x in inputs[:n1]]
-    res = {}
-    drain(ids1, res)
-    sat_rate = n1 / (time.perf_counter() - t0)
-    lam = 0.7 * sat_rate
+    all_engines = {"plain_fp32": mh.FP32_FIELD, "matrix_bf16x3": mh.BF16X3_WM}
+    engines = {k: v for k, v in all_engines.items() if k.split("_")[0] in args.engines.split(",")}
+    out = {}
+    for name, prec in engines.items():
+        sat = serve(prec, geo[:n_sat], [0.0] * n_sat, f"{name} saturation")
+        out[name] = {"saturated": dict(sat, req_per_s=n_sat / sat["seconds"])}
+    # arrival rates are factors of the plain engine's saturated rate (measured here, or
+    # given when the engines run in separate processes)
+    lam0 = args.lambda0 or out["plain_fp32"]["saturated"]["req_per_s"]
     rng = np.random.default_rng(77)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(inputs) - n1))
-    ids2 = []
-    t1 = time.perf_counter()
-    for x, ta in zip(inputs[n1:], arrivals):
-        while time.perf_counter() - t1 < ta:
-            time.sleep(0.0005)
-        ids2.append(srv.submit(x[0], x[1], x[2], seed=x[3]["seed"], target_rel_err=0.01,
-                               min_replicas=64, max_replicas=maxr))
-    drain(ids2, res)
-    t2 = time.perf_counter()
-    srv.close()
-    lat = np.array([(res[i]["done_ns"] - res[i]["submit_ns"]) / 1e9 for i in ids2])
-    loops = sum(res[i]["loops"] for i in ids2)
-    npsteps = sum(x[0].shape[0] * 2000 * x[3]["P"] * res[i]["replicas"] for x, i in zip(inputs[n1:], ids2))
-    rel = [2 * res[i]["area_se"] / max(abs(res[i]["area_Jm3"]), 1e-300) for i in ids2]
-    line = {"metric": "served loops/s; p50/p99 request latency", "value": loops / (t2 - t1),
-            "unit": "loops/s", "n_gpus": 1, "steps": len(ids2), "warmup": n1,
-            "ms_per_step": (t2 - t1) / max(len(ids2), 1) * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None,
-            "dtype": "bf16x3 mfma / f64 barrier" if prec == mh.BF16X3_WM else "f32 field / f64 barrier",
+    for k, fct in enumerate(rates):
+        items = geo[n_sat + k * n_rate:n_sat + (k + 1) * n_rate]
+        gaps = np.cumsum(rng.exponential(1.0 / (fct * lam0), size=len(items)))
+        gaps -= gaps[0]
+        for name, prec in engines.items():
+            out[name][f"rate_{fct:g}x"] = dict(serve(prec, items, gaps, f"{name} {fct:g}x"),
+                                               arrival_req_per_s=fct * lam0)
+    eng = out.get("matrix_bf16x3") or out["plain_fp32"]
+    main = eng.get("rate_0.7x") or eng["saturated"]
+    return {"metric": "served loops/s; p50/p99 request latency at SAR err<=1%",
+            "value": main["loops_per_s"], "unit": "loops/s", "n_gpus": 1,
+            "steps": n_rate * len(rates), "warmup": n_sat,
+            "ms_per_step": main["seconds"] / max(main["requests"], 1) * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16x3 mfma / f64 barrier (value); f32 field / f64 barrier (plain)",
             "data": "synthetic",
-            "config": {"workload": f"served request stream ({args.workload}): Poisson arrivals at 0.7 x saturated rate "
-                                   f"({lam:.3f} req/s), {len(ids2)} timed requests after {n1} saturation ones",
-                       "p50_latency_s": float(np.percentile(lat, 50)),
-                       "p99_latency_s": float(np.percentile(lat, 99)),
-                       "np_steps_per_s": npsteps / (t2 - t1),
-                       "saturated_req_per_s": sat_rate,
-                       "replicas_per_request_median": float(np.median([res[i]["replicas"] for i in ids2])),
-                       "two_se_over_area_median": float(np.median(rel)),
-                       "max_replicas": maxr}}
-    print(json.dumps(line), flush=True)
+            "config": {"workload": f"served request stream: {n_sat} saturation requests per engine, "
+                                   f"then {n_rate} Poisson arrivals at each of {rates} x the plain "
+                                   f"engine's saturated rate ({lam0:.4g} req/s); value: "
+                                   f"{'matrix' if 'matrix_bf16x3' in out else 'plain'} engine "
+                                   f"at 0.7x",
+                       "max_replicas": args.max_replicas, "target_two_se_over_area": 0.01,
+                       "engines": out}}
 
 
 def bench_uneven256(args, mh, W):

@@ -799,13 +799,16 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     if ((e = c->d_kbase.ensure(sizeof(int64_t)))) return e;
     int64_t* kb = c->d_kbase.as<int64_t>();
     // the captured kernels read the plan from d_sys at fixed offsets: reuse the graph
-    // while the uploaded plan has the same layout
+    // while the uploaded plan has the same layout (every pointer and count a captured
+    // launch takes is part of the key)
     std::vector<uint64_t> key = {(uint64_t)(uintptr_t)c->d_sys.p, (uint64_t)off, (uint64_t)G};
     for (int gi = 0; gi < kGroups; ++gi) {
       key.push_back((uint64_t)(uintptr_t)d_til[gi]);
+      key.push_back((uint64_t)(uintptr_t)d_tiles[gi]);
       key.push_back(pl.tiles[gi].size());
     }
     key.push_back((uint64_t)(uintptr_t)d_upd);
+    key.push_back((uint64_t)(uintptr_t)d_ublocks);
     key.push_back(pl.ublocks.size());
     key.push_back(pl.scan_upd ? 1 : 0);
     for (auto& it : pl.wm) {
@@ -1808,6 +1811,8 @@ struct mh_server {
   int64_t round_size = 64;
   int error = 0;
   std::thread th;
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};  // end of the last two enqueued chunks
+  int64_t chunk_no = 0;
   void loop();
   int start_round(SReq* q);
   int finish_round(SReq* q, bool& done);
@@ -1922,7 +1927,16 @@ void mh_server::loop() {
     o.finalize = false;
     o.k0 = clock;
     o.k1 = clock + chunk;
-    int e = run_systems(v, R, S, ctx->stream, o);
+    // bounded run-ahead: the host enqueues a chunk only once the chunk before the
+    // previous one has finished, so a request admitted now starts within about two
+    // chunks instead of behind a long queue of enqueued ones
+    int e = MH_OK;
+    hipEvent_t& ev = chunk_ev[chunk_no & 1];
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) e = MH_EDEVICE;
+    if (!e && chunk_no >= 2 && hipEventSynchronize(ev) != hipSuccess) e = MH_EDEVICE;
+    if (!e) e = run_systems(v, R, S, ctx->stream, o);
+    if (!e && hipEventRecord(ev, ctx->stream) != hipSuccess) e = MH_EDEVICE;
+    ++chunk_no;
     clock += chunk;
     std::vector<SReq*> still;
     for (auto* q : running) {
@@ -2042,6 +2056,8 @@ int mh_server_destroy(mh_server* s) {
     if (kv.second->a) mh_destroy_assembly(kv.second->a);
     delete kv.second;
   }
+  for (hipEvent_t ev : s->chunk_ev)
+    if (ev) (void)hipEventDestroy(ev);
   mh_ctx_destroy(s->ctx);
   delete s;
   return MH_OK;
