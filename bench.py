@@ -615,9 +615,9 @@ def bench_served(args, mh, W):
             ids.append(srv.submit(pos, axes, params(prec, q), seed=q["seed"], target_rel_err=0.01,
                                   abs_err_floor=0.0, min_replicas=64,
                                   max_replicas=args.max_replicas))
-        out = {}
+        out, seen = {}, {}
         while len(out) < len(ids):
-            for i in ids:
+            for k, i in enumerate(ids):
                 if i not in out:
                     r = srv.poll(i)
                     if r is not None:
@@ -625,6 +625,12 @@ def bench_served(args, mh, W):
                         print(f"served {label}: {len(out)}/{len(ids)} done, {r['replicas']} "
                               f"replicas, {(r['done_ns'] - r['submit_ns']) / 1e9:.2f} s",
                               file=sys.stderr, flush=True)
+                    else:
+                        done_r = srv.progress(i)
+                        if done_r != seen.get(i, 0):   # a round of this request finished
+                            seen[i] = done_r
+                            print(f"served {label}: request {k} at {done_r} replicas",
+                                  file=sys.stderr, flush=True)
             time.sleep(0.002)
         srv.close()
         res = [out[i] for i in ids]

@@ -295,7 +295,10 @@ int mh_server_create(mh_ctx* ctx, size_t hbm_budget_bytes, mh_server** out);
 /* Copies the request; MH_EBUDGET if it can never fit the budget, MH_EOVERLAP/MH_EINVAL
  * for invalid inputs. Thread-safe. */
 int mh_server_submit(mh_server* s, const mh_request* req, uint64_t* req_id);
-/* MH_ENOTREADY until the request finished; then fills *out. Thread-safe. */
+/* Fills *out with the result once the request finished (MH_OK). Before that returns
+ * MH_ENOTREADY and fills *out with its progress only: replicas = replicas of the rounds
+ * finished so far, submit_ns and start_ns (0 while queued), status MH_ENOTREADY, the
+ * rest zero. Thread-safe. */
 int mh_server_poll(mh_server* s, uint64_t req_id, mh_result* out);
 /* Stops after the admitted requests finish (queued ones are dropped) and frees all. */
 int mh_server_destroy(mh_server* s);

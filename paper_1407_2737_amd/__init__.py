@@ -367,6 +367,14 @@ class Server:
         _check(rc, "mh_server_poll")
         return {f: getattr(res, f) for f, _ in Result._fields_}
 
+    def progress(self, rid: int) -> int:
+        """Replicas finished so far (all of them once the request is done)."""
+        res = Result()
+        rc = _lib().mh_server_poll(self._h, rid, C.byref(res))
+        if rc not in (0, ENOTREADY):
+            _check(rc, "mh_server_poll")
+        return res.replicas
+
     def close(self):
         if self._h:
             _lib().mh_server_destroy(self._h)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <array>
@@ -1763,6 +1764,7 @@ struct SReq {
   size_t bytes = 0;
   DevBuf areas;  // per-replica areas of finished rounds
   mh_result res{};
+  std::atomic<int64_t> progress{0};  // replicas of finished rounds, for polls in flight
 };
 
 // Device memory a request holds while admitted: its geometry and the buffers that
@@ -1851,6 +1853,7 @@ int mh_server::finish_round(SReq* q, bool& done) {
                      sizeof(double) * q->round_R, hipMemcpyDeviceToDevice, st) != hipSuccess)
     return MH_EDEVICE;
   q->done_R += q->round_R;
+  q->progress.store(q->done_R, std::memory_order_relaxed);
   if (launch_finalize_asm(q->areas.as<double>(), (int)q->done_R, q->a->stats.as<double>(), st) !=
       hipSuccess)
     return MH_EDEVICE;
@@ -2039,7 +2042,15 @@ int mh_server_poll(mh_server* s, uint64_t req_id, mh_result* out) {
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->reqs.find(req_id);
   if (it == s->reqs.end()) return MH_EINVAL;
-  if (it->second->state != 2) return MH_ENOTREADY;
+  if (it->second->state != 2) {
+    // progress so far: replicas of the rounds finished, no result yet
+    *out = mh_result{};
+    out->replicas = it->second->progress.load(std::memory_order_relaxed);
+    out->submit_ns = it->second->res.submit_ns;
+    out->start_ns = it->second->res.start_ns;
+    out->status = MH_ENOTREADY;
+    return MH_ENOTREADY;
+  }
   *out = it->second->res;
   return MH_OK;
 }

@@ -99,4 +99,5 @@ def test_budget_counts_axis_sets_and_state(lib):
     i = srv.submit(pos, W.axes_random_3d(n, 73), p, seed=1, min_replicas=1, max_replicas=1)
     r = _wait(srv, [i])[i]
     assert r["status"] == 0 and r["replicas"] == 1
+    assert srv.progress(i) == 1      # a finished request reports all its replicas
     srv.close()

@@ -149,3 +149,22 @@ def test_field_error_per_result(ctx, lib):
             e_or = np.linalg.norm(got - ref) / np.linalg.norm(ref)
             assert abs(e_or - rel) < 0.05 * rel + 1e-12
         a.close()
+
+
+def test_wm_replicas_independent_of_replica_count(ctx, lib):
+    """Replicas of the matrix form are independent systems sharing only W: replicas
+    0..255 of a 512-replica run (one axis set per replica; two replica tiles of the
+    product) are bitwise those of a 256-replica run of the same assembly."""
+    n = 700
+    pos = W.place_random(n, 110e-9, 12e-9, 911)
+    axes = W.axes_random_3d(n * 512, 912)
+    kw = _kw(steps_per_period=100, n_periods=2, n_discard=1)
+    a = lib.Assembly(ctx, pos, axes, lib.Params.make(lib.BF16X3_WM, **kw), n_axes_sets=512)
+    a.run(256, seed=13)
+    a.sync()
+    ar256, m256 = a.replica_areas().copy(), a.moments(255).copy()
+    a.run(512, seed=13)
+    a.sync()
+    assert np.array_equal(a.replica_areas()[:256], ar256)
+    assert np.array_equal(a.moments(255), m256)
+    a.close()
