@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--sat-requests", type=int, default=8, help="served: saturation requests")
     ap.add_argument("--rates", default="0.5,0.7,0.9", help="served: factors of the plain "
                     "engine's saturated request rate")
-    ap.add_argument("--max-replicas", type=int, default=2048)
+    ap.add_argument("--max-replicas", type=int, default=512)
     ap.add_argument("--engines", default="plain,matrix", help="served: plain and/or matrix")
     ap.add_argument("--lambda0", type=float, default=0.0,
                     help="served: the plain engine's saturated request rate (req/s) when it "
@@ -615,6 +615,8 @@ def bench_served(args, mh, W):
             ids.append(srv.submit(pos, axes, params(prec, q), seed=q["seed"], target_rel_err=0.01,
                                   abs_err_floor=0.0, min_replicas=64,
                                   max_replicas=args.max_replicas))
+            print(f"served {label}: request {len(ids) - 1} submitted (N={q['n']}, "
+                  f"{q['P']} periods)", file=sys.stderr, flush=True)
         out, seen = {}, {}
         while len(out) < len(ids):
             for k, i in enumerate(ids):

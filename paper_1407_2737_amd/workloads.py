@@ -261,8 +261,10 @@ def request_stream(count: int = 1000, seed: int = 1005, rate_hz: float = 1.0):
     """Poisson arrivals of loop requests: N log-uniform in [100, 8000], radius
     U(80,300) nm, phi U(1,20) % (d derived), f log-uniform in [1e5, 1e6] Hz, mu0Hmax
     U(5,50) mT, periods U{3..10} with one discarded."""
+    # request parameters and arrival gaps from separate generators, so that the first k
+    # requests are the same whatever the count
     rng = np.random.default_rng(seed)
-    t = np.cumsum(rng.exponential(1.0 / rate_hz, size=count))
+    t = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / rate_hz, size=count))
     reqs = []
     for q in range(count):
         n = int(round(math.exp(rng.uniform(math.log(100), math.log(8000)))))
