@@ -16,16 +16,16 @@
 // W is never stored: each block generates its W tile stage by stage from the
 // positions (FP64 differences, FP32 r^-3 and r^-5 terms, then the hi/lo split), so
 // the only operand streamed from memory is M^T. Generation costs about a quarter of
-// the block's MFMA time in VALU work, which the other wave of each SIMD overlaps.
+// the block's MFMA time in VALU work, issued between the wave's own MFMAs.
 //
 // Tiling: block = 8 waves, tile = 256 replicas x 192 matrix rows (64 target particles)
 // over half of k (two k splits whose partial products the update kernel adds in fixed
 // order), k-stage 48 (16 source particles). Thread (tp, c) = (tid / 8, tid % 8)
 // generates the 3x3 blocks of target tp with sources 2c and 2c + 1 of the next stage
 // (rows 3 tp .. 3 tp + 2, columns 6 c .. 6 c + 5) into the other LDS buffer (hi and
-// lo, rows padded to 56 bf16 so that 16-byte fragment reads do not conflict) while
-// the current stage's MFMAs run; the stage's 16 source positions are staged in LDS one
-// stage earlier. Each wave owns 32 replicas x 192 rows (six 32x32 accumulators) and
+// lo, rows padded to 56 bf16 so that 16-byte fragment reads do not conflict), a third
+// per k-step, its VALU work interleaved with that k-step's MFMAs (two VALU per MFMA);
+// the stage's 16 source positions are staged in LDS one stage earlier. Each wave owns 32 replicas x 192 rows (six 32x32 accumulators) and
 // loads its M^T fragments straight from global memory, one stage ahead. An XCD (block
 // index mod 8) works on one (k split, replica tile) pair where the shape allows it, so
 // its blocks share one M^T slab in its L2.
@@ -210,47 +210,52 @@ __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
     // keep the next stage's loads in flight across the MFMAs
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    auto mfmas = [&]() {
+    float t0[9], t1[9];
+    const int j0 = jbeg + 16 * (st + 1) + 2 * c;
+    const int pbn = (st + 1) & 1;
 #pragma unroll
-      for (int s = 0; s < WM_SUB; ++s) {
-        const int kk = (lane >> 5) * 24 + s * 8;
-        bf16x8 bh[6], bl[6];
+    for (int s = 0; s < WM_SUB; ++s) {
+      const int kk = (lane >> 5) * 24 + s * 8;
+      bf16x8 bh[6], bl[6];
 #pragma unroll
-        for (int u = 0; u < 6; ++u) {
-          bh[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][0][u * 32 + (lane & 31)][kk]);
-          bl[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][1][u * 32 + (lane & 31)][kk]);
-        }
-        // the three split products sweep the six accumulators in turn, so consecutive
-        // MFMAs never depend on each other
-#pragma unroll
-        for (int u = 0; u < 6; ++u)
-          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bh[u], acc[u], 0, 0, 0);
-#pragma unroll
-        for (int u = 0; u < 6; ++u)
-          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[1][s], bh[u], acc[u], 0, 0, 0);
-#pragma unroll
-        for (int u = 0; u < 6; ++u)
-          acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bl[u], acc[u], 0, 0, 0);
+      for (int u = 0; u < 6; ++u) {
+        bh[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][0][u * 32 + (lane & 31)][kk]);
+        bl[u] = *reinterpret_cast<const bf16x8*>(&Ws[cur][1][u * 32 + (lane & 31)][kk]);
       }
-    };
-    // W of the next stage from the staged positions. Waves w and w + 4 share a SIMD:
-    // the first half generates before its MFMAs and the second after them, so that on
-    // each SIMD one wave's VALU work runs beside the other's MFMAs (wave-uniform branch)
-    if (w < 4) {
-      if (more) generate(st + 1);
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bh[u], acc[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[1][s], bh[u], acc[u], 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 6; ++u)
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ac[0][s], bl[u], acc[u], 0, 0, 0);
+      // a third of the next stage's W per k-step, between this k-step's MFMAs (also in
+      // the last stage, where the sources are padding and nothing reads the result)
+      if (s == 0) pair_block(pt.x, pt.y, pt.z, tgt_ok, Ps[pbn][2 * c], j0 == it, t0);
+      if (s == 1) pair_block(pt.x, pt.y, pt.z, tgt_ok, Ps[pbn][2 * c + 1], j0 + 1 == it, t1);
+      if (s == 2) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          split_pack(t0[3 * a], t0[3 * a + 1], gh[3 * a], gl[3 * a]);
+          split_pack(t0[3 * a + 2], t1[3 * a], gh[3 * a + 1], gl[3 * a + 1]);
+          split_pack(t1[3 * a + 1], t1[3 * a + 2], gh[3 * a + 2], gl[3 * a + 2]);
+        }
+        store_w(cur ^ 1);  // free: every wave finished reading it before the last barrier
+      }
+      __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);  // the k-step's LDS reads first
+#pragma unroll
+      for (int q = 0; q < 18; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // then up to 2 VALU
+      }
       __builtin_amdgcn_sched_barrier(0);
-      mfmas();
-    } else {
-      mfmas();
-      __builtin_amdgcn_sched_barrier(0);
-      if (more) generate(st + 1);
     }
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     if (more) {
-      // every wave has finished reading Ws[cur ^ 1] (stage st - 1) and Ps[st & 1]
-      // (generated into W of stage st) before the previous barrier
-      store_w(cur ^ 1);
+      // Ps[st & 1] (read for W of stage st + 1 above) takes the sources of stage st + 2
       if (tid < 16) Ps[st & 1][tid] = pnext;
       __syncthreads();
     }
