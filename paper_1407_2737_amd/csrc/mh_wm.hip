@@ -25,10 +25,11 @@
 // (rows 3 tp .. 3 tp + 2, columns 6 c .. 6 c + 5) into the other LDS buffer (hi and
 // lo, rows padded to 56 bf16 so that 16-byte fragment reads do not conflict), a third
 // per k-step, its VALU work interleaved with that k-step's MFMAs (two VALU per MFMA);
-// the stage's 16 source positions are staged in LDS one stage earlier. Each wave owns 32 replicas x 192 rows (six 32x32 accumulators) and
-// loads its M^T fragments straight from global memory, one stage ahead. An XCD (block
-// index mod 8) works on one (k split, replica tile) pair where the shape allows it, so
-// its blocks share one M^T slab in its L2.
+// the stage's 16 source positions are staged in LDS one stage earlier. Each wave owns
+// 32 replicas x 192 rows (six 32x32 accumulators) and loads its M^T fragments straight
+// from global memory, each k-step's fragment one stage ahead. An XCD (block index mod
+// 8) works on one (k split, replica tile) pair where the shape allows it, so its
+// blocks share one M^T slab in its L2.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -127,15 +128,14 @@ __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
   const size_t aoff = (size_t)(rep0 >> 5) * nkb * WM_SUB * 512 + (size_t)lane * 8;
   const __bf16* ah = g.mhi + aoff;
   const __bf16* al = g.mlo + aoff;
-  bf16x8 an[2][WM_SUB];  // next stage M^T fragments [hi/lo][k-step]
-#define MH_LOAD_A(st_)                                                           \
-  do {                                                                           \
-    const size_t o_ = (size_t)(kbeg / WM_BK + (st_)) * (WM_SUB * 512);           \
-    _Pragma("unroll") for (int s = 0; s < WM_SUB; ++s) {                         \
-      an[0][s] = *reinterpret_cast<const bf16x8*>(ah + o_ + s * 512);            \
-      an[1][s] = *reinterpret_cast<const bf16x8*>(al + o_ + s * 512);            \
-    }                                                                            \
-  } while (0)
+  // M^T fragments of the stage's k-steps [hi/lo][k-step]: slot s is reloaded with k-step s
+  // of the next stage as soon as the MFMAs of k-step s are issued
+  bf16x8 ac[2][WM_SUB];
+  auto load_a = [&](int st_, int s) {
+    const size_t o = (size_t)(kbeg / WM_BK + st_) * (WM_SUB * 512) + (size_t)s * 512;
+    ac[0][s] = *reinterpret_cast<const bf16x8*>(ah + o);
+    ac[1][s] = *reinterpret_cast<const bf16x8*>(al + o);
+  };
   // generation: target tp of the block, sources 2c, 2c+1 of a stage
   const int tp = tid >> 3, c = tid & 7;
   const int it = rt * 64 + tp;
@@ -185,7 +185,8 @@ __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
     for (int e = 0; e < 16; ++e) acc[u][e] = 0.f;
 
   // prologue: source positions of stages 0 and 1, W of stage 0, M^T of stage 0
-  MH_LOAD_A(0);
+#pragma unroll
+  for (int s = 0; s < WM_SUB; ++s) load_a(0, s);
   if (tid < 16) {
     Ps[0][tid] = src_of(0);
     Ps[1][tid] = src_of(1);
@@ -196,17 +197,9 @@ __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int cur = st & 1;
-    bf16x8 ac[2][WM_SUB];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int s = 0; s < WM_SUB; ++s) ac[h][s] = an[h][s];
     const bool more = st + 1 < nst;
     D4 pnext = {0.0, 0.0, 0.0, 0.0};
-    if (more) {
-      MH_LOAD_A(st + 1);
-      if (tid < 16) pnext = src_of(st + 2);
-    }
+    if (more && tid < 16) pnext = src_of(st + 2);
     // keep the next stage's loads in flight across the MFMAs
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
@@ -244,6 +237,7 @@ __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
         }
         store_w(cur ^ 1);  // free: every wave finished reading it before the last barrier
       }
+      if (more) load_a(st + 1, s);
       __builtin_amdgcn_sched_group_barrier(0x100, 12, 0);  // the k-step's LDS reads first
 #pragma unroll
       for (int q = 0; q < 18; ++q) {
@@ -260,7 +254,6 @@ __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
       __syncthreads();
     }
   }
-#undef MH_LOAD_A
   // partial B^T of k split ks: lane holds column wrow0 + u*32 + lane%32 of rows
   // rep0 + 8*(e/4) + 4*(lane/32) + e%4
   float* bt = g.bt + (size_t)ks * g.Rp * g.Mp;
