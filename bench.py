@@ -590,7 +590,7 @@ def bench_served(args, mh, W):
     plain engine's saturated rate, on a fresh server. Reported per engine and rate:
     kept loops/s, p50/p99 request latency, and the achieved 2 SE / area."""
     import numpy as np
-    rates = [float(x) for x in args.rates.split(",")]
+    rates = [float(x) for x in args.rates.split(",") if x.strip()]  # "": saturation only
     n_sat, n_rate = args.sat_requests, args.requests
     reqs = W.request_stream(count=n_sat + n_rate * len(rates), seed=1005, rate_hz=1.0)
     geo = []

@@ -70,6 +70,18 @@ struct WMArgs {
   int n_ctiles;    // Rp / WM_BM
 };
 
+// One system's share of a launch that covers several matrix-form systems: its
+// operands and its range of blocks (product: row tiles x replica tiles x k splits; update:
+// nbx particle blocks of 256 x R replicas, its replica 0 at index `first` of the launch's
+// descriptor array).
+struct WMGroupItem {
+  WMArgs g;
+  int32_t boff;   // first block of the item in the launch
+  int32_t nb;     // blocks of the item
+  int32_t first;  // update: descriptor index of replica 0
+  int32_t nbx;    // update: particle blocks per replica
+};
+
 __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {
   if (s.static_field) return s.Bmax;
   return s.Bmax * cos(2.0 * kPi * (double)k / (double)s.S);

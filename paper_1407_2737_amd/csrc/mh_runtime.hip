@@ -44,6 +44,11 @@ int wm_ksplit();
 hipError_t launch_wm_gemm(const WMArgs& g, hipStream_t st);
 hipError_t launch_wm_update(bool scan, const SysDesc* d_sys, int R, int n, const WMArgs& g,
                             const int64_t* kbase, int64_t koff, hipStream_t st);
+hipError_t launch_wm_gemm_group(const WMGroupItem* d_items, int nitems, int nblocks,
+                               hipStream_t st);
+hipError_t launch_wm_update_group(bool scan, const SysDesc* d_all, const WMGroupItem* d_items,
+                                  int nitems, int nblocks, const int64_t* kbase, int64_t koff,
+                                  hipStream_t st);
 hipError_t launch_wm_pack(const SysDesc* d_sys, int R, int n, const WMArgs& g, int b,
                           hipStream_t st);
 hipError_t launch_finalize(const SysDesc* d_sys, int nsys, hipStream_t st);
@@ -134,6 +139,11 @@ struct ShapeEntry {
 struct mh_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // Input uploads (assembly creation). Non-blocking: a server's submit runs on the
+  // caller's thread while the server thread may be capturing a graph on `stream`, and a
+  // copy on the legacy stream would take an implicit dependency on that capture, which
+  // the runtime rejects.
+  hipStream_t upload = nullptr;
   int n_cu = 256;
   DevBuf d_sys;
   PinBuf h_stage;
@@ -499,6 +509,10 @@ struct Plan {
   std::vector<SysDesc> res64, res32, til[kGroups];
   std::vector<int4> tiles[kGroups];
   std::vector<WMItem> wm;
+  // two or more matrix-form systems: one product launch and one update launch per
+  // extremum mode cover them all (wmu[1]: the 200-point scan)
+  std::vector<WMGroupItem> wmg, wmu[2];
+  int wmg_blocks = 0, wmu_blocks[2] = {0, 0};
   std::vector<SysDesc> upd;   // all tiled systems
   std::vector<int2> ublocks;  // (system in upd, block of 256 particles)
   int nmax_res64 = 0, nmax_res32 = 0;
@@ -538,6 +552,44 @@ void add_tiled(Plan& pl, int fp64, int kind, const std::vector<SysDesc>& reps, i
     const int uidx = (int)pl.upd.size();
     pl.upd.push_back(s);
     for (int b = 0; b < s.ntiles; ++b) pl.ublocks.push_back(int2{uidx, b});
+  }
+}
+
+// Block ranges of the grouped matrix-form launches. Products go longest first (the
+// longest k range, then the most blocks), each range starting at a multiple of 8 so that
+// every block keeps its XCD; updates go largest first. A block's work is the same as
+// in the system's own launch, so the results do not depend on the grouping.
+void group_wm(Plan& pl) {
+  std::vector<int> ord(pl.wm.size());
+  for (size_t q = 0; q < ord.size(); ++q) ord[q] = (int)q;
+  auto gemm_blocks = [](const WMArgs& g) { return g.n_rtiles * g.n_ctiles * wm_ksplit(); };
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    const WMArgs &a = pl.wm[x].g, &b = pl.wm[y].g;
+    return a.Kp != b.Kp ? a.Kp > b.Kp : gemm_blocks(a) > gemm_blocks(b);
+  });
+  for (int q : ord) {
+    const WMItem& it = pl.wm[q];
+    WMGroupItem x{};
+    x.g = it.g;
+    x.boff = pl.wmg_blocks;
+    x.nb = gemm_blocks(it.g);
+    pl.wmg.push_back(x);
+    pl.wmg_blocks += (x.nb + 7) / 8 * 8;
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    return pl.wm[x].a->n * pl.wm[x].a->R > pl.wm[y].a->n * pl.wm[y].a->R;
+  });
+  for (int q : ord) {
+    const WMItem& it = pl.wm[q];
+    const int sc = it.a->p.extrema_mode == MH_EXTREMA_SCAN200 ? 1 : 0;
+    WMGroupItem x{};
+    x.g = it.g;
+    x.first = it.first;
+    x.nbx = (int)((it.a->n + 255) / 256);
+    x.nb = x.nbx * (int)it.a->R;
+    x.boff = pl.wmu_blocks[sc];
+    pl.wmu[sc].push_back(x);
+    pl.wmu_blocks[sc] += x.nb;
   }
 }
 
@@ -678,6 +730,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     fin.push_back({a, {first, (int)all.size()}});
     if (a->p.precision == MH_BF16X3_WM) pl.wm.push_back(WMItem{a, first, wm_args(a)});
   }
+  if (pl.wm.size() >= 2) group_wm(pl);
   // descriptors and tile lists, laid out as one blob; a plan identical to the one the
   // context staged last (a server chunk of the same requests) is not uploaded again
   PlanBlob blob;
@@ -688,6 +741,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     o_tiles[gi] = blob.put(pl.tiles[gi]);
   }
   const size_t o_upd = blob.put(pl.upd), o_ublocks = blob.put(pl.ublocks);
+  const size_t o_wmg = blob.put(pl.wmg), o_wmu0 = blob.put(pl.wmu[0]), o_wmu1 = blob.put(pl.wmu[1]);
   const size_t off = blob.h.size();
   int e;
   if (!(c->d_sys.p && off <= c->d_sys.cap && blob.h == c->staged)) {
@@ -712,6 +766,27 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   }
   SysDesc* d_upd = blob_ptr<SysDesc>(c, o_upd);
   int2* d_ublocks = blob_ptr<int2>(c, o_ublocks);
+  WMGroupItem* d_wmg = blob_ptr<WMGroupItem>(c, o_wmg);
+  WMGroupItem* d_wmu[2] = {blob_ptr<WMGroupItem>(c, o_wmu0), blob_ptr<WMGroupItem>(c, o_wmu1)};
+  // the matrix-form launches of one step: kind 2 the products, kind 4 the updates
+  auto wm_launches = [&](int kind, const int64_t* kb, int64_t koff) -> hipError_t {
+    hipError_t r = hipSuccess;
+    if (pl.wm.size() >= 2) {
+      if (kind == 2) return launch_wm_gemm_group(d_wmg, (int)pl.wmg.size(), pl.wmg_blocks, st);
+      for (int sc = 0; sc < 2 && r == hipSuccess; ++sc)
+        if (!pl.wmu[sc].empty())
+          r = launch_wm_update_group(sc == 1, d_all, d_wmu[sc], (int)pl.wmu[sc].size(),
+                                     pl.wmu_blocks[sc], kb, koff, st);
+      return r;
+    }
+    for (auto& it : pl.wm) {
+      if (r != hipSuccess) break;
+      r = kind == 2 ? launch_wm_gemm(it.g, st)
+                    : launch_wm_update(it.a->p.extrema_mode == MH_EXTREMA_SCAN200, d_all + it.first,
+                                       (int)it.a->R, (int)it.a->n, it.g, kb, koff, st);
+    }
+    return r;
+  };
   if (o.init) {
     if (launch_init(d_all, (int)all.size(), pl.nmax_all, st) != hipSuccess) return MH_EDEVICE;
   } else if (o.sync32) {
@@ -738,13 +813,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       } else if (o.time_kind == 3) {
         r = launch_update(pl.scan_upd, d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st);
       } else {
-        for (auto& it : pl.wm) {
-          if (r != hipSuccess) break;
-          r = o.time_kind == 2
-                  ? launch_wm_gemm(it.g, st)
-                  : launch_wm_update(it.a->p.extrema_mode == MH_EXTREMA_SCAN200, d_all + it.first,
-                                     (int)it.a->R, (int)it.a->n, it.g, kb, koff, st);
-        }
+        r = wm_launches(o.time_kind == 2 ? 2 : 4, kb, koff);
       }
       return r == hipSuccess ? MH_OK : MH_EDEVICE;
     };
@@ -781,15 +850,12 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
         hipSuccess)
       return MH_EDEVICE;
     timing_end(c, st, t0);
-    for (auto& it : pl.wm) {
+    if (!pl.wm.empty()) {
       t0 = timing_begin(c, st, 2);
-      if (launch_wm_gemm(it.g, st) != hipSuccess) return MH_EDEVICE;
+      if (wm_launches(2, kb, koff) != hipSuccess) return MH_EDEVICE;
       timing_end(c, st, t0);
       t0 = timing_begin(c, st, 4);
-      if (launch_wm_update(it.a->p.extrema_mode == MH_EXTREMA_SCAN200, d_all + it.first,
-                           (int)it.a->R, (int)it.a->n, it.g, kb, koff, st) !=
-          hipSuccess)
-        return MH_EDEVICE;
+      if (wm_launches(4, kb, koff) != hipSuccess) return MH_EDEVICE;
       timing_end(c, st, t0);
     }
     return MH_OK;
@@ -819,6 +885,12 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
       key.push_back((uint64_t)it.a->R);
       key.push_back((uint64_t)it.a->p.extrema_mode);
     }
+    key.push_back((uint64_t)(uintptr_t)d_wmg);
+    key.push_back((uint64_t)(uintptr_t)d_wmu[0]);
+    key.push_back((uint64_t)(uintptr_t)d_wmu[1]);
+    key.push_back((uint64_t)pl.wmg_blocks);
+    key.push_back((uint64_t)pl.wmu_blocks[0]);
+    key.push_back((uint64_t)pl.wmu_blocks[1]);
     if (!c->gexec || key != c->gkey) {
       if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
@@ -1178,9 +1250,15 @@ int mh_ctx_create(int device, mh_ctx** out) {
     delete c;
     return MH_EDEVICE;
   }
+  if (hipStreamCreateWithFlags(&c->upload, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+    return MH_EDEVICE;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->n_cu = prop.multiProcessorCount;
   if (set_resident_lds_limit() != hipSuccess || scratch_address(device, &c->scratch)) {
+    (void)hipStreamDestroy(c->upload);
     (void)hipStreamDestroy(c->stream);
     delete c;
     return MH_EDEVICE;
@@ -1202,6 +1280,7 @@ int mh_ctx_destroy(mh_ctx* c) {
   c->d_kbase.release();
   c->d_sys.release();
   c->h_stage.release();
+  (void)hipStreamDestroy(c->upload);
   (void)hipStreamDestroy(c->stream);
   delete c;
   return MH_OK;
@@ -1251,10 +1330,16 @@ int mh_create_assembly_sets(mh_ctx* c, int64_t n, const double* pos, int64_t n_p
     mh_destroy_assembly(a);
     return e;
   }
-  if (hipMemcpy(a->pos64.p, p64.data(), sizeof(D4) * np, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(a->pos32.p, p32.data(), sizeof(F4) * np, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(a->axes.p, ax.data(), sizeof(D4) * n * n_axes_sets, hipMemcpyHostToDevice) !=
-          hipSuccess) {
+  // on the context's upload stream (the buffers are new: no earlier work touches them),
+  // complete before the assembly is returned
+  hipStream_t up = c->upload;
+  if (hipMemcpyAsync(a->pos64.p, p64.data(), sizeof(D4) * np, hipMemcpyHostToDevice, up) !=
+          hipSuccess ||
+      hipMemcpyAsync(a->pos32.p, p32.data(), sizeof(F4) * np, hipMemcpyHostToDevice, up) !=
+          hipSuccess ||
+      hipMemcpyAsync(a->axes.p, ax.data(), sizeof(D4) * n * n_axes_sets, hipMemcpyHostToDevice,
+                     up) != hipSuccess ||
+      hipStreamSynchronize(up) != hipSuccess) {
     mh_destroy_assembly(a);
     return MH_EDEVICE;
   }

@@ -94,29 +94,33 @@ __device__ __forceinline__ void pair_block(double px, double py, double pz, bool
   t[8] = dz * uz - c3;
 }
 
-__global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 Ws[2][2][WM_BN][WM_LD];
-  __shared__ D4 Ps[2][16];
+typedef __bf16 WTile[2][2][WM_BN][WM_LD];  // generated W tiles [buffer][hi/lo][row][k]
+typedef D4 PStage[2][16];                     // source positions of two stages
+
+// Block bid of the product of g, whose blocks are numbered 0 .. nb_range - 1 in a range
+// of the launch that starts at a multiple of 8 (bid mod 8 is then the block's XCD).
+__device__ __forceinline__ void wm_gemm_block(const WMArgs& g, int bid, int nb_range, WTile& Ws,
+                                              PStage& Ps) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   // block -> (W row tile, k split, replica tile). XCD-aware when the shape allows it:
   // the C = n_ctiles * WM_SK (k split, replica tile) pairs each get 8 / C XCDs, so the
   // blocks of an XCD read one M^T slab, from that XCD's L2
   int rt, ks, ct;
+  const unsigned ub = (unsigned)bid;
   const int nb = g.n_rtiles * g.n_ctiles * WM_SK;
   const int C = g.n_ctiles * WM_SK;
-  if ((C == 1 || C == 2 || C == 4 || C == 8) && nb == (int)gridDim.x &&
-      g.n_rtiles % (8 / C) == 0) {
+  if ((C == 1 || C == 2 || C == 4 || C == 8) && nb == nb_range && g.n_rtiles % (8 / C) == 0) {
     const int X = 8 / C;  // XCDs per pair
-    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int xcd = ub & 7, slot = ub >> 3;
     const int pair = xcd / X;
     ks = pair % WM_SK;
     ct = pair / WM_SK;
     rt = (xcd % X) * (g.n_rtiles / X) + slot;
   } else {
-    ct = blockIdx.x % g.n_ctiles;
-    ks = (blockIdx.x / g.n_ctiles) % WM_SK;
-    rt = blockIdx.x / (g.n_ctiles * WM_SK);
+    ct = ub % g.n_ctiles;
+    ks = (ub / g.n_ctiles) % WM_SK;
+    rt = ub / (g.n_ctiles * WM_SK);
   }
   const int wrow0 = rt * WM_BN;           // first W row (output column) of the block
   const int rep0 = ct * WM_BM + w * 32;   // the wave's 32 replicas (output rows)
@@ -267,6 +271,33 @@ __global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
     }
 }
 
+__global__ __launch_bounds__(512) void k_wm_gemm(WMArgs g) {
+  __shared__ __attribute__((aligned(16))) WTile Ws;
+  __shared__ PStage Ps;
+  wm_gemm_block(g, blockIdx.x, gridDim.x, Ws, Ps);
+}
+
+// Item of a launch that covers several systems' products or matrix-form updates: the
+// items own consecutive block ranges, in the order the host chose.
+__device__ __forceinline__ int wm_item_of(const WMGroupItem* __restrict__ items, int nitems) {
+  int q = 0;
+  while (q + 1 < nitems && (int)blockIdx.x >= items[q + 1].boff) ++q;
+  return q;
+}
+
+// The products of several systems in one launch (block ranges start at multiples of 8,
+// so each block keeps the XCD it has in a launch of its own and computes the same tile).
+__global__ __launch_bounds__(512) void k_wm_gemm_group(const WMGroupItem* __restrict__ items,
+                                                       int nitems) {
+  __shared__ __attribute__((aligned(16))) WTile Ws;
+  __shared__ PStage Ps;
+  const int q = wm_item_of(items, nitems);
+  const int bid = (int)blockIdx.x - items[q].boff;
+  if (bid >= items[q].nb) return;
+  const WMArgs g = items[q].g;
+  wm_gemm_block(g, bid, items[q].nb, Ws, Ps);
+}
+
 // hi/lo split of the moments of replica r, particle i into M^T.
 __device__ __forceinline__ void store_split(const WMArgs& g, int r, int i, double mx, double my,
                                             double mz) {
@@ -294,16 +325,15 @@ __global__ void k_wm_pack(const SysDesc* __restrict__ systems, WMArgs g, int b) 
 // Per-particle update of the matrix form: thread (r, i) reads its three reduced field
 // components from B^T, runs steps iii-vii and writes the new moment (FP64 state and the
 // hi/lo split for the next product).
+// Block (bx, r) covers particles 256 bx .. 256 bx + 255 of replica r.
 template <bool kScan>
-__global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ systems, WMArgs g,
-                                                   const int64_t* __restrict__ kbase,
-                                                   int64_t koff) {
-  __shared__ double red[4];
-  const int r = blockIdx.y;
+__device__ __forceinline__ void wm_update_block(const SysDesc* __restrict__ systems,
+                                                const WMArgs& g, const int64_t* __restrict__ kbase,
+                                                int64_t koff, int bx, int r, double* red) {
   const SysDesc& s = systems[r];
   const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = bx * 256 + threadIdx.x;
   const int cur = (int)(k & 1);
   double mx = 0.0;
   if (i < s.n) {
@@ -326,7 +356,7 @@ __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ s
     double v = mx;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    double* rp = s.recpart + ((k - s.kept0) * s.ntiles + blockIdx.x) * s.rec_slots;
+    double* rp = s.recpart + ((k - s.kept0) * s.ntiles + bx) * s.rec_slots;
     if (s.rec_slots == kRecSlots) {
       if ((threadIdx.x & 63) == 0) rp[threadIdx.x >> 6] = v;
     } else {  // uniform over the block
@@ -335,6 +365,31 @@ __global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ s
       if (threadIdx.x == 0) rp[0] = (red[0] + red[1]) + (red[2] + red[3]);
     }
   }
+}
+
+template <bool kScan>
+__global__ __launch_bounds__(256) void k_wm_update(const SysDesc* __restrict__ systems, WMArgs g,
+                                                   const int64_t* __restrict__ kbase,
+                                                   int64_t koff) {
+  __shared__ double red[4];
+  wm_update_block<kScan>(systems, g, kbase, koff, blockIdx.x, blockIdx.y, red);
+}
+
+// The matrix-form updates of several systems in one launch: item q owns nb = nbx x R
+// blocks from boff on, block boff + r nbx + bx being (bx, r) of its own launch.
+template <bool kScan>
+__global__ __launch_bounds__(256) void k_wm_update_group(const SysDesc* __restrict__ all,
+                                                         const WMGroupItem* __restrict__ items,
+                                                         int nitems,
+                                                         const int64_t* __restrict__ kbase,
+                                                         int64_t koff) {
+  __shared__ double red[4];
+  const int q = wm_item_of(items, nitems);
+  const int lb = (int)blockIdx.x - items[q].boff;
+  if (lb >= items[q].nb) return;
+  const int nbx = items[q].nbx;
+  const WMArgs g = items[q].g;
+  wm_update_block<kScan>(all + items[q].first, g, kbase, koff, lb % nbx, lb / nbx, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -358,6 +413,24 @@ hipError_t launch_wm_update(bool scan, const SysDesc* d_sys, int R, int n, const
   else
     hipLaunchKernelGGL(k_wm_update<false>, dim3((n + 255) / 256, R), dim3(256), 0, st, d_sys, g,
                        kbase, koff);
+  return hipGetLastError();
+}
+
+hipError_t launch_wm_gemm_group(const WMGroupItem* d_items, int nitems, int nblocks,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_wm_gemm_group, dim3(nblocks), dim3(512), 0, st, d_items, nitems);
+  return hipGetLastError();
+}
+
+hipError_t launch_wm_update_group(bool scan, const SysDesc* d_all, const WMGroupItem* d_items,
+                                  int nitems, int nblocks, const int64_t* kbase, int64_t koff,
+                                  hipStream_t st) {
+  if (scan)
+    hipLaunchKernelGGL(k_wm_update_group<true>, dim3(nblocks), dim3(256), 0, st, d_all, d_items,
+                       nitems, kbase, koff);
+  else
+    hipLaunchKernelGGL(k_wm_update_group<false>, dim3(nblocks), dim3(256), 0, st, d_all, d_items,
+                       nitems, kbase, koff);
   return hipGetLastError();
 }
 

@@ -101,3 +101,25 @@ def test_budget_counts_axis_sets_and_state(lib):
     assert r["status"] == 0 and r["replicas"] == 1
     assert srv.progress(i) == 1      # a finished request reports all its replicas
     srv.close()
+
+
+def test_submit_while_the_server_captures(lib):
+    """Requests are submitted from the caller's thread while the server thread captures
+    and replays the graphs of earlier requests (each admission changes the plan, so the
+    server captures again): every submission must be accepted and every request must
+    finish. The assembly upload of a submission runs on a non-blocking stream, so it
+    takes no implicit dependency on the server's capturing stream."""
+    ctx = lib.Context(0)
+    srv = lib.Server(ctx, 32 << 30)
+    forms = [lib.BF16X3_WM, lib.FP32_FIELD, lib.BF16X3_WM, lib.FP64]
+    ids = []
+    for q in range(24):
+        n = (120, 500, 260, 80)[q % 4] + 7 * q
+        req = _req(lib, n, forms[q % 4], 300 + q, S=100, P=3)
+        ids.append(srv.submit(*req, seed=q, target_rel_err=0.5, min_replicas=64,
+                              max_replicas=256 if forms[q % 4] == lib.BF16X3_WM else 64))
+        time.sleep(0.002 * (q % 5))
+    res = _wait(srv, ids, timeout=300)
+    srv.close()
+    assert all(res[i]["status"] == 0 for i in ids)
+    assert all(res[i]["replicas"] >= 64 for i in ids)

@@ -168,3 +168,38 @@ def test_wm_replicas_independent_of_replica_count(ctx, lib):
     assert np.array_equal(a.replica_areas()[:256], ar256)
     assert np.array_equal(a.moments(255), m256)
     a.close()
+
+
+def test_wm_group_launch_equals_alone(ctx, lib):
+    """Several matrix-form assemblies in one batch share one product launch and one update
+    launch per extremum mode. Each block computes what it computes in the assembly's own
+    launch, so every result must be bitwise that of the assembly run alone: sizes from
+    one to four row-tile groups, one and two replica tiles, one member in the 200-point
+    scan mode, through the captured graph (200 steps) and again from the same graph."""
+    specs = [(90, 3, 0), (1100, 17, 0), (300, 300, 0), (700, 40, 1), (2000, 5, 0)]
+    mem = []
+    for q, (n, R, scan) in enumerate(specs):
+        pos = W.place_random(n, 12e-9 / 2 * (n / 0.08) ** (1 / 3), 12e-9, 930 + q)
+        axes = W.axes_random_3d(n, 940 + q)
+        kw = _kw(steps_per_period=100, n_periods=2, n_discard=1,
+                 mu0Hmax=0.01 + 0.005 * q, extrema_mode=scan)
+        mem.append((pos, axes, kw, R, 50 + q))
+    alone = []
+    for pos, axes, kw, R, seed in mem:
+        a = lib.Assembly(ctx, pos, axes, lib.Params.make(lib.BF16X3_WM, **kw))
+        a.run(R, seed)
+        a.sync()
+        alone.append((a.replica_areas().copy(), a.moments(R - 1).copy(), a.loop(0, 0)[1].copy()))
+        a.close()
+    asms = [lib.Assembly(ctx, pos, axes, lib.Params.make(lib.BF16X3_WM, **kw))
+            for pos, axes, kw, R, seed in mem]
+    for rep in range(2):
+        lib.run_batch(asms, [m[3] for m in mem], [m[4] for m in mem])
+        for q, a in enumerate(asms):
+            a.sync()
+            R = mem[q][3]
+            assert np.array_equal(a.replica_areas(), alone[q][0]), (rep, q)
+            assert np.array_equal(a.moments(R - 1), alone[q][1]), (rep, q)
+            assert np.array_equal(a.loop(0, 0)[1], alone[q][2]), (rep, q)
+    for a in asms:
+        a.close()
