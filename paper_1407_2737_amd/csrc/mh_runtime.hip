@@ -144,6 +144,11 @@ struct mh_ctx {
   // copy on the legacy stream would take an implicit dependency on that capture, which
   // the runtime rejects.
   hipStream_t upload = nullptr;
+  // The resident systems of a run that also has tiled ones: their whole-run launch goes
+  // here, forked from and joined back to the run's stream, so that it runs beside the
+  // tiled steps instead of before them (created on first use).
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int n_cu = 256;
   DevBuf d_sys;
   PinBuf h_stage;
@@ -825,101 +830,123 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   const int64_t k1 = o.k1 < 0 ? pl.kmax : o.k1;
   const bool any_res = !pl.res64.empty() || !pl.res32.empty();
   bool any_til = !pl.wm.empty() || !pl.ublocks.empty();
-  int tq = any_res && k1 > k0 ? timing_begin(c, st, 1) : -1;
+  // resident systems beside the tiled steps: they share no buffer but the (read-only)
+  // plan, and the run's stream waits for them before the finalisation
+  const bool beside = any_res && any_til && k1 > k0;
+  hipStream_t rst = st;
+  if (beside) {
+    if (!c->side && (hipStreamCreate(&c->side) != hipSuccess ||
+                     hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+                     hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess))
+      return MH_EDEVICE;
+    if (hipEventRecord(c->fork_ev, st) != hipSuccess ||
+        hipStreamWaitEvent(c->side, c->fork_ev, 0) != hipSuccess)
+      return MH_EDEVICE;
+    rst = c->side;
+  }
+  int tq = any_res && k1 > k0 ? timing_begin(c, rst, 1) : -1;
   if (launch_resident(true, pl.scan_res64, d_res64, (int)pl.res64.size(), k0, k1, pl.nmax_res64,
-                      st) != hipSuccess)
+                      rst) != hipSuccess)
     return MH_EDEVICE;
   if (launch_resident(false, pl.scan_res32, d_res32, (int)pl.res32.size(), k0, k1, pl.nmax_res32,
-                      st) != hipSuccess)
+                      rst) != hipSuccess)
     return MH_EDEVICE;
-  timing_end(c, st, tq);
-  // one tiled step: dipolar fields, then the per-particle update
-  auto step = [&](const int64_t* kb, int64_t koff) -> int {
-    int t0 = timing_begin(c, st, 0);
-    for (int f = 0; f < 2; ++f)
-      for (int kd = 0; kd < 2; ++kd)
-        for (int G = 1; G <= 4; ++G) {
-          const int gi = gidx(f, kd, G);
-          if (launch_field(f == 1, kd, G, d_til[gi], d_tiles[gi], (int)pl.tiles[gi].size(), kb,
-                           koff, st) != hipSuccess)
-            return MH_EDEVICE;
+  timing_end(c, rst, tq);
+  if (beside && hipEventRecord(c->join_ev, rst) != hipSuccess) return MH_EDEVICE;
+  // the tiled steps; whatever their outcome, the run's stream then waits for the
+  // resident launch (an error must not leave it reading a plan that may be re-staged)
+  const int rc_til = [&]() -> int {
+    // one tiled step: dipolar fields, then the per-particle update
+    auto step = [&](const int64_t* kb, int64_t koff) -> int {
+      int t0 = timing_begin(c, st, 0);
+      for (int f = 0; f < 2; ++f)
+        for (int kd = 0; kd < 2; ++kd)
+          for (int G = 1; G <= 4; ++G) {
+            const int gi = gidx(f, kd, G);
+            if (launch_field(f == 1, kd, G, d_til[gi], d_tiles[gi], (int)pl.tiles[gi].size(), kb,
+                             koff, st) != hipSuccess)
+              return MH_EDEVICE;
+          }
+      timing_end(c, st, t0);
+      t0 = timing_begin(c, st, 3);
+      if (launch_update(pl.scan_upd, d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st) !=
+          hipSuccess)
+        return MH_EDEVICE;
+      timing_end(c, st, t0);
+      if (!pl.wm.empty()) {
+        t0 = timing_begin(c, st, 2);
+        if (wm_launches(2, kb, koff) != hipSuccess) return MH_EDEVICE;
+        timing_end(c, st, t0);
+        t0 = timing_begin(c, st, 4);
+        if (wm_launches(4, kb, koff) != hipSuccess) return MH_EDEVICE;
+        timing_end(c, st, t0);
+      }
+      return MH_OK;
+    };
+    int64_t k = k0;
+    constexpr int64_t G = 50;
+    if (any_til && c->use_graphs && !c->timing && k1 - k0 >= 2 * G) {
+      if ((e = c->d_kbase.ensure(sizeof(int64_t)))) return e;
+      int64_t* kb = c->d_kbase.as<int64_t>();
+      // the captured kernels read the plan from d_sys at fixed offsets: reuse the graph
+      // while the uploaded plan has the same layout (every pointer and count a captured
+      // launch takes is part of the key)
+      std::vector<uint64_t> key = {(uint64_t)(uintptr_t)c->d_sys.p, (uint64_t)off, (uint64_t)G};
+      for (int gi = 0; gi < kGroups; ++gi) {
+        key.push_back((uint64_t)(uintptr_t)d_til[gi]);
+        key.push_back((uint64_t)(uintptr_t)d_tiles[gi]);
+        key.push_back(pl.tiles[gi].size());
+      }
+      key.push_back((uint64_t)(uintptr_t)d_upd);
+      key.push_back((uint64_t)(uintptr_t)d_ublocks);
+      key.push_back(pl.ublocks.size());
+      key.push_back(pl.scan_upd ? 1 : 0);
+      for (auto& it : pl.wm) {
+        const uint64_t* gw = reinterpret_cast<const uint64_t*>(&it.g);
+        for (size_t q = 0; q < sizeof(WMArgs) / 8; ++q) key.push_back(gw[q]);
+        key.push_back((uint64_t)it.first);
+        key.push_back((uint64_t)it.a->R);
+        key.push_back((uint64_t)it.a->p.extrema_mode);
+      }
+      key.push_back((uint64_t)(uintptr_t)d_wmg);
+      key.push_back((uint64_t)(uintptr_t)d_wmu[0]);
+      key.push_back((uint64_t)(uintptr_t)d_wmu[1]);
+      key.push_back((uint64_t)pl.wmg_blocks);
+      key.push_back((uint64_t)pl.wmu_blocks[0]);
+      key.push_back((uint64_t)pl.wmu_blocks[1]);
+      if (!c->gexec || key != c->gkey) {
+        if (c->gexec) {
+          (void)hipGraphExecDestroy(c->gexec);
+          c->gexec = nullptr;
         }
-    timing_end(c, st, t0);
-    t0 = timing_begin(c, st, 3);
-    if (launch_update(pl.scan_upd, d_upd, d_ublocks, (int)pl.ublocks.size(), kb, koff, st) !=
-        hipSuccess)
-      return MH_EDEVICE;
-    timing_end(c, st, t0);
-    if (!pl.wm.empty()) {
-      t0 = timing_begin(c, st, 2);
-      if (wm_launches(2, kb, koff) != hipSuccess) return MH_EDEVICE;
-      timing_end(c, st, t0);
-      t0 = timing_begin(c, st, 4);
-      if (wm_launches(4, kb, koff) != hipSuccess) return MH_EDEVICE;
-      timing_end(c, st, t0);
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+          return MH_EDEVICE;
+        int rc = MH_OK;
+        for (int64_t j = 0; j < G && rc == MH_OK; ++j) rc = step(kb, j);
+        if (rc == MH_OK && launch_set_step(kb, G, true, st) != hipSuccess) rc = MH_EDEVICE;
+        if (hipStreamEndCapture(st, &g) != hipSuccess || rc != MH_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return MH_EDEVICE;
+        }
+        const hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+          c->gexec = nullptr;
+          return MH_EDEVICE;
+        }
+        c->gkey = key;
+      }
+      if (launch_set_step(kb, k0, false, st) != hipSuccess) return MH_EDEVICE;
+      for (; k + G <= k1; k += G)
+        if (hipGraphLaunch(c->gexec, st) != hipSuccess) return MH_EDEVICE;
     }
+    for (; k < k1 && any_til; ++k)
+      if ((e = step(nullptr, k))) return e;
     return MH_OK;
-  };
-  int64_t k = k0;
-  constexpr int64_t G = 50;
-  if (any_til && c->use_graphs && !c->timing && k1 - k0 >= 2 * G) {
-    if ((e = c->d_kbase.ensure(sizeof(int64_t)))) return e;
-    int64_t* kb = c->d_kbase.as<int64_t>();
-    // the captured kernels read the plan from d_sys at fixed offsets: reuse the graph
-    // while the uploaded plan has the same layout (every pointer and count a captured
-    // launch takes is part of the key)
-    std::vector<uint64_t> key = {(uint64_t)(uintptr_t)c->d_sys.p, (uint64_t)off, (uint64_t)G};
-    for (int gi = 0; gi < kGroups; ++gi) {
-      key.push_back((uint64_t)(uintptr_t)d_til[gi]);
-      key.push_back((uint64_t)(uintptr_t)d_tiles[gi]);
-      key.push_back(pl.tiles[gi].size());
-    }
-    key.push_back((uint64_t)(uintptr_t)d_upd);
-    key.push_back((uint64_t)(uintptr_t)d_ublocks);
-    key.push_back(pl.ublocks.size());
-    key.push_back(pl.scan_upd ? 1 : 0);
-    for (auto& it : pl.wm) {
-      const uint64_t* gw = reinterpret_cast<const uint64_t*>(&it.g);
-      for (size_t q = 0; q < sizeof(WMArgs) / 8; ++q) key.push_back(gw[q]);
-      key.push_back((uint64_t)it.first);
-      key.push_back((uint64_t)it.a->R);
-      key.push_back((uint64_t)it.a->p.extrema_mode);
-    }
-    key.push_back((uint64_t)(uintptr_t)d_wmg);
-    key.push_back((uint64_t)(uintptr_t)d_wmu[0]);
-    key.push_back((uint64_t)(uintptr_t)d_wmu[1]);
-    key.push_back((uint64_t)pl.wmg_blocks);
-    key.push_back((uint64_t)pl.wmu_blocks[0]);
-    key.push_back((uint64_t)pl.wmu_blocks[1]);
-    if (!c->gexec || key != c->gkey) {
-      if (c->gexec) {
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
-      }
-      hipGraph_t g = nullptr;
-      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return MH_EDEVICE;
-      int rc = MH_OK;
-      for (int64_t j = 0; j < G && rc == MH_OK; ++j) rc = step(kb, j);
-      if (rc == MH_OK && launch_set_step(kb, G, true, st) != hipSuccess) rc = MH_EDEVICE;
-      if (hipStreamEndCapture(st, &g) != hipSuccess || rc != MH_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return MH_EDEVICE;
-      }
-      const hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (ie != hipSuccess) {
-        c->gexec = nullptr;
-        return MH_EDEVICE;
-      }
-      c->gkey = key;
-    }
-    if (launch_set_step(kb, k0, false, st) != hipSuccess) return MH_EDEVICE;
-    for (; k + G <= k1; k += G)
-      if (hipGraphLaunch(c->gexec, st) != hipSuccess) return MH_EDEVICE;
-  }
-  for (; k < k1 && any_til; ++k)
-    if ((e = step(nullptr, k))) return e;
+  }();
+  if (beside && hipStreamWaitEvent(st, c->join_ev, 0) != hipSuccess) return MH_EDEVICE;
+  if (rc_til) return rc_til;
   if (o.finalize) {
     if (launch_finalize(d_all, (int)all.size(), st) != hipSuccess) return MH_EDEVICE;
     for (auto& f : fin) {
@@ -1280,6 +1307,12 @@ int mh_ctx_destroy(mh_ctx* c) {
   c->d_kbase.release();
   c->d_sys.release();
   c->h_stage.release();
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+    (void)hipEventDestroy(c->fork_ev);
+    (void)hipEventDestroy(c->join_ev);
+  }
   (void)hipStreamDestroy(c->upload);
   (void)hipStreamDestroy(c->stream);
   delete c;
