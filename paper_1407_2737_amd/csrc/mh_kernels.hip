@@ -413,9 +413,10 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
   const int cur = (int)(k & 1);
   double mx = 0.0;
   if (i < s.n) {
+    const NPState st = np_state(s, i, cur);
     double fx, fy, fz;
     sum_parts(s, i, fx, fy, fz);  // partial sums of the source parts, fixed order
-    mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz);
+    mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz, st);
   }
   if (k >= s.kept0 && !s.field_only) {  // the loop record: wave sums or their total
     double v = mx;
@@ -480,21 +481,10 @@ __global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ sys
   Dir d1{0.0, 0.0};
   double u = 0.0;
   if (act) {
-    for (int p = 0; p < s.nsplit; ++p) {  // partial sums of the source parts, fixed order
-      if (s.field32) {
-        const F4 f = s.field32[(int64_t)p * s.n + i];
-        fx += (double)f.x;
-        fy += (double)f.y;
-        fz += (double)f.z;
-      } else {
-        const D4 f = s.field[(int64_t)p * s.n + i];
-        fx += f.x;
-        fy += f.y;
-        fz += f.z;
-      }
-    }
+    const NPState st = np_state(s, i, cur);
+    sum_parts(s, i, fx, fy, fz);  // partial sums of the source parts, fixed order
     if (!s.field_only && s.np.aniso) {
-      q = np_in(s, i, k, cur, fx, fy, fz);
+      q = np_in(s, k, fx, fy, fz, st.mo, st.nn);
       w = working_plane(s.np, q.Bx, q.By, q.Bz, q.nn.x, q.nn.y, q.nn.z, q.mo.x, q.mo.y, q.mo.z);
       general = w.hy != 0.0 && w.hx != 0.0;
     }

@@ -223,13 +223,23 @@ __device__ __forceinline__ double np_out(const SysDesc& s, int i, int64_t k, int
   return mh_new;
 }
 
+// The moment of particle i in buffer cur and its axis: loaded before the field sums
+// are added, so that these loads and the partial-sum loads make one memory round trip.
+struct NPState {
+  D4 mo, nn;
+};
+__device__ __forceinline__ NPState np_state(const SysDesc& s, int i, int cur) {
+  return NPState{ldg(s.m64 + (int64_t)cur * s.stride + i), ldg(s.axes + i)};
+}
+
 // Steps iii-vii for particle i of system s with the reduced dipolar sum (ax, ay, az)
-// from the moments in buffer cur; writes buffer cur^1, accumulates the area, and
-// returns the new moment's component along the field direction e_H. kScan as for
+// from the moment and axis st (buffer cur); writes buffer cur^1, accumulates the area,
+// and returns the new moment's component along the field direction e_H. kScan as for
 // np_update.
 template <bool kScan>
 __device__ __forceinline__ double np_epilogue(const SysDesc& s, int i, int64_t k, int cur,
-                                              double ax, double ay, double az) {
+                                              double ax, double ay, double az,
+                                              const NPState& st) {
   if (s.field_only) {
     double* d = s.diag + (int64_t)i * 8;
     d[0] = s.Bscale * ax;
@@ -238,10 +248,16 @@ __device__ __forceinline__ double np_epilogue(const SysDesc& s, int i, int64_t k
     return 0.0;
   }
   np_dhdip(s, i, k, ax, ay, az);
-  const NPIn q = np_in(s, i, k, cur, ax, ay, az);
+  const NPIn q = np_in(s, k, ax, ay, az, st.mo, st.nn);
   const NPResult r = np_update<kScan>(s.np, q.Bx, q.By, q.Bz, q.nn.x, q.nn.y, q.nn.z, q.mo.x,
                                       q.mo.y, q.mo.z, s.seed, s.stream, i, k);
   return np_out(s, i, k, cur, q, r);
+}
+
+template <bool kScan>
+__device__ __forceinline__ double np_epilogue(const SysDesc& s, int i, int64_t k, int cur,
+                                              double ax, double ay, double az) {
+  return np_epilogue<kScan>(s, i, k, cur, ax, ay, az, np_state(s, i, cur));
 }
 
 }  // namespace mh

@@ -337,6 +337,7 @@ __device__ __forceinline__ void wm_update_block(const SysDesc* __restrict__ syst
   const int cur = (int)(k & 1);
   double mx = 0.0;
   if (i < s.n) {
+    const NPState st = np_state(s, i, cur);
     // partial products of the k splits, added in fixed order
     double fx = 0.0, fy = 0.0, fz = 0.0;
 #pragma unroll
@@ -346,7 +347,7 @@ __device__ __forceinline__ void wm_update_block(const SysDesc* __restrict__ syst
       fy += (double)f[1];
       fz += (double)f[2];
     }
-    mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz);
+    mx = np_epilogue<kScan>(s, i, k, cur, fx, fy, fz, st);
     if (!s.field_only) {
       const D4 m = s.m64[(int64_t)(cur ^ 1) * s.stride + i];
       store_split(g, r, i, m.x, m.y, m.z);
