@@ -287,8 +287,18 @@ __global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ s
   const int4 tlv = tiles[blockIdx.x];  // (first system, i-tile, replicas, part), uniform
   const int4 tl = make_int4(__builtin_amdgcn_readfirstlane(tlv.x), __builtin_amdgcn_readfirstlane(tlv.y),
                             __builtin_amdgcn_readfirstlane(tlv.z), __builtin_amdgcn_readfirstlane(tlv.w));
+  const int64_t kb0 = step_base(kbase, systems);
   const SysDesc& s = systems[tl.x];
-  const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
+  // with the prefetched fields, what the first staging loads need, in the same batch:
+  // positions, field scale and the moment buffers of the block's replicas
+  const P4* gpos = pos_of<T>(s);
+  const double bscale = s.Bscale;
+  const P4* gm0[G];
+#pragma unroll
+  for (int r = 0; r < G; ++r) gm0[r] = mom_of<T>(systems[tl.x + (r < tl.z ? r : 0)]);
+  desc_prefetch(s, gpos, gm0[0], G > 1 ? gm0[G > 1 ? 1 : 0] : nullptr,
+                G > 2 ? gm0[G > 2 ? 2 : 0] : nullptr, G > 3 ? gm0[G > 3 ? 3 : 0] : nullptr, bscale);
+  const int64_t k = kb0 + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;
   const int n = s.n;
   const int gn = tl.z;
@@ -298,18 +308,16 @@ __global__ __launch_bounds__(1024, 8) void k_field(const SysDesc* __restrict__ s
   const int q = w * L + l / TI;
   const int i = tl.y * TI + il;
   const int cur = (int)(k & 1);
-  const P4* gpos = pos_of<T>(s);
   const P4* gmom[G];
 #pragma unroll
-  for (int r = 0; r < G; ++r)
-    gmom[r] = mom_of<T>(systems[tl.x + (r < gn ? r : 0)]) + (int64_t)cur * s.stride;
+  for (int r = 0; r < G; ++r) gmom[r] = gm0[r] + (int64_t)cur * s.stride;
   T bx[G], by[G], bz[G];
 #pragma unroll
   for (int r = 0; r < G; ++r) bx[r] = by[r] = bz[r] = (T)0;
   // sources of this block: part tl.w of nsplit equal parts (multiples of Q)
   const int per = ((n + s.nsplit - 1) / s.nsplit + Q - 1) / Q * Q;
   const int jb = tl.w * per, je = min(n, jb + per);
-  if (s.Bscale != 0.0 && n > 1) {
+  if (bscale != 0.0 && n > 1) {
     const P4 pi = gpos[i < n ? i : n - 1];
     const T xi = (T)pi.x, yi = (T)pi.y, zi = (T)pi.z;
     for (int c0 = jb; c0 < je; c0 += CH) {
@@ -406,8 +414,10 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
   const int2 blv = blocks[blockIdx.x];
   const int2 bl = make_int2(__builtin_amdgcn_readfirstlane(blv.x),
                             __builtin_amdgcn_readfirstlane(blv.y));
+  const int64_t kb0 = step_base(kbase, systems);
   const SysDesc& s = systems[bl.x];
-  const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
+  desc_prefetch(s);
+  const int64_t k = kb0 + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;
   const int i = bl.y * 256 + threadIdx.x;
   const int cur = (int)(k & 1);
@@ -466,8 +476,10 @@ __global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ sys
   const int2 bl = make_int2(__builtin_amdgcn_readfirstlane(blv.x),
                             __builtin_amdgcn_readfirstlane(blv.y));
   const int part = (int)(blockIdx.x & 3);  // sub-block = wave of the 256-particle block
+  const int64_t kb0 = step_base(kbase, systems);
   const SysDesc& s = systems[bl.x];
-  const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
+  desc_prefetch(s);
+  const int64_t k = kb0 + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;                      // uniform over the block
   const int role = threadIdx.x >> 6, t = threadIdx.x & 63;
   const int i = bl.y * 256 + part * 64 + t;

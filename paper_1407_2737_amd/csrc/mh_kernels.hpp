@@ -82,6 +82,37 @@ struct WMGroupItem {
   int32_t nbx;    // update: particle blocks per replica
 };
 
+// Reads the descriptor fields that a kernel's step-window test and first data loads
+// depend on, all ahead of any branch, and holds them together in scalar registers: the
+// scalar loads are then issued back to back and share one wait, where the compiler would
+// otherwise place each behind the branch that first needs it (one round trip each).
+// Later reads of these fields reuse the values (the descriptors are not written by the
+// kernels that read them).
+// The step base of a launch: *kbase (a captured graph's device-side counter), or 0
+// without one. The load itself is unconditional (from `fallback`, any readable address,
+// when kbase is null), so it is issued with the launch's first scalar loads rather than
+// behind a branch.
+__device__ __forceinline__ int64_t step_base(const int64_t* kbase, const void* fallback) {
+  const int64_t v = *(kbase ? kbase : reinterpret_cast<const int64_t*>(fallback));
+  return kbase ? v : 0;
+}
+
+__device__ __forceinline__ void desc_prefetch(const SysDesc& s, const void* e0 = nullptr,
+                                              const void* e1 = nullptr, const void* e2 = nullptr,
+                                              const void* e3 = nullptr, const void* e4 = nullptr,
+                                              double e5 = 0.0) {
+  // e0..e5: further uniform values the caller read from descriptors, held in the same
+  // batch
+  const int64_t ko = s.k_origin, sd = s.stride;
+  const int32_t n = s.n, ts = s.total_steps, np = s.nsplit, fo = s.field_only;
+  const void* q0 = s.m64;
+  const void* q1 = s.axes;
+  const void* q2 = s.field32;
+  const void* q3 = s.field;
+  asm volatile("" ::"s"(ko), "s"(sd), "s"(n), "s"(ts), "s"(np), "s"(fo), "s"(q0), "s"(q1), "s"(q2),
+               "s"(q3), "s"(e0), "s"(e1), "s"(e2), "s"(e3), "s"(e4), "s"(e5));
+}
+
 __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {
   if (s.static_field) return s.Bmax;
   return s.Bmax * cos(2.0 * kPi * (double)k / (double)s.S);

@@ -330,8 +330,10 @@ template <bool kScan>
 __device__ __forceinline__ void wm_update_block(const SysDesc* __restrict__ systems,
                                                 const WMArgs& g, const int64_t* __restrict__ kbase,
                                                 int64_t koff, int bx, int r, double* red) {
+  const int64_t kb0 = step_base(kbase, systems);
   const SysDesc& s = systems[r];
-  const int64_t k = (kbase ? *kbase : 0) + koff - s.k_origin;  // local step
+  desc_prefetch(s);
+  const int64_t k = kb0 + koff - s.k_origin;  // local step
   if (k < 0 || k >= s.total_steps) return;
   const int i = bx * 256 + threadIdx.x;
   const int cur = (int)(k & 1);
