@@ -46,7 +46,7 @@ ALG_BYTES_PER_NP = 48           # HBM bytes per particle and system per step of 
 # WRITE_SIZE over the default workload, each scaled by what the counter reads for a
 # 256 MiB elementwise copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000); tied to the kernel
 # as measured (profiles/k_field_n5000x3_fp32.md). None where no such measurement exists.
-TRAFFIC_BYTES = {"k_field<float,16,3>": (1413.19 * 2.000 + 703.13 * 1.000) * 1024}
+TRAFFIC_BYTES = {"k_field<float,16,3>": (1412.69 * 2.000 + 703.13 * 1.000) * 1024}
 
 
 _POOL_ASM = None  # the workload the pooled oracle leg steps (set before the fork)
