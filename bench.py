@@ -284,6 +284,8 @@ def bench_n100(args, mh, W):
             asm.sync()
         out[R] = (time.perf_counter() - t0) / args.steps
     sar = asm.sar()
+    # latency floor of a resident step: one LDS exchange and one barrier per step
+    us_empty = ctx.time_empty_steps(steps_per_run)
     # the whole run is one resident launch: its duration from one event pair
     ctx.set_timing(True)
     asm.run(1024, seed=a1.seed)
@@ -299,6 +301,8 @@ def bench_n100(args, mh, W):
             "config": {"workload": "N=100 in an 80 nm lysosome, d=12 nm, 20 mT, 100 kHz, "
                                    "3 periods x 2000 steps, FP64, 1024 replicas",
                        "us_per_time_step_one_replica": out[1] / steps_per_run * 1e6,
+                       "us_per_empty_resident_step": us_empty,
+                       "one_replica_step_over_empty": out[1] / steps_per_run * 1e6 / us_empty,
                        "sar_W_per_g": sar["sar"] / 1e3, "sar_se_W_per_g": sar["sar_se"] / 1e3},
             "roofline": _roof("alu", flops, us_launch, PEAK_FP64_VECTOR, "TFLOP/s",
                               "k_resident<double> (whole run; pair terms only counted)",

@@ -346,6 +346,17 @@ int mh_ctx_get_timing(mh_ctx* ctx, int32_t kind, double* total_ms, int64_t* laun
 int mh_time_kernels(mh_asm* const* asms, int32_t count, int32_t kind, int32_t launches,
                     int32_t reps, double* us_per_step);
 
+/* Latency floor of a resident step (diagnostics for the latency-bound small-system
+ * form). The step scheme of Sec. II.1 makes every step depend on the previous one (the
+ * field of step k uses the moments after step k - 1), so a system run by one workgroup
+ * pays at least one exchange through LDS and one barrier per step. This launches one
+ * workgroup of the resident kernel's size that runs `steps` such empty steps (each
+ * thread reads a neighbour's value of the previous step from one LDS buffer, writes its
+ * own to the other, then the barrier) between two HIP events on the context's stream;
+ * *us_per_step = their time / steps. Synchronous. MH_EINVAL for steps outside
+ * [1, 1e7] or a null argument. */
+int mh_time_empty_steps(mh_ctx* ctx, int64_t steps, double* us_per_step);
+
 const char* mh_strerror(int code);
 
 #ifdef __cplusplus

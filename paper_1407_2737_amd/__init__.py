@@ -29,7 +29,7 @@ SYMBOLS = [
     "mh_set_replica_fields", "mh_get_area_per_np", "mh_run_mean_loop",
     "mh_ctx_autotune", "mh_ctx_load_shapes", "mh_get_dhdip",
     "mh_get_local_concentration", "mh_create_assembly_sets", "mh_get_field_error",
-    "mh_debug_sw_mode", "mh_field_noalloc", "mh_time_kernels",
+    "mh_debug_sw_mode", "mh_field_noalloc", "mh_time_kernels", "mh_time_empty_steps",
 ]
 
 
@@ -98,6 +98,7 @@ def _lib():
             "mh_run_loops": ([vp, i64, u64, vp], C.c_int),
             "mh_run_batch": ([C.POINTER(vp), i32, C.POINTER(i64), u64p, vp], C.c_int),
             "mh_time_kernels": ([C.POINTER(vp), i32, i32, i32, i32, dp], C.c_int),
+            "mh_time_empty_steps": ([vp, i64, dp], C.c_int),
             "mh_sync": ([vp], C.c_int),
             "mh_get_loop": ([vp, i64, i32, dp, dp], C.c_int),
             "mh_get_sar": ([vp, dp, dp, dp, dp, dp], C.c_int),
@@ -170,6 +171,13 @@ class Context:
 
     def set_timing(self, on: bool):
         _check(_lib().mh_ctx_set_timing(self._h, 1 if on else 0), "mh_ctx_set_timing")
+
+    def time_empty_steps(self, steps: int = 6000) -> float:
+        """mh_time_empty_steps: microseconds per empty resident step (one LDS exchange and
+        one barrier in one workgroup), the latency floor of a resident step."""
+        us = C.c_double()
+        _check(_lib().mh_time_empty_steps(self._h, steps, C.byref(us)), "mh_time_empty_steps")
+        return us.value
 
     def get_timing(self, kind: int = 0):
         """(summed ms, launches) of the recorded step-kernel launches of one kind."""

@@ -151,6 +151,21 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
   while (P < 64 && 2 * P * n <= kResThreads) P *= 2;
   const int per_pass = kResThreads / P;
   const int sub = tid % P;
+  // A system that takes one pass per step gives each updating thread the same particle
+  // in every step: its axis and area accumulator are held in registers for the whole
+  // launch, its FP64 moment is read from the LDS copy (FP64 systems) and the new one is
+  // written there from registers, so the step's chain makes no global memory round trip
+  // (the state in memory is written as before; field-only evaluations, whose
+  // descriptors may carry no area buffer, keep the general path).
+  const int i_own = tid / P;
+  const bool own = n <= per_pass && sub == 0 && i_own < n && !s.field_only;
+  D4 nn_own = {0.0, 0.0, 0.0, 0.0};
+  double acc[2] = {0.0, 0.0};
+  if (own) {
+    nn_own = s.axes[i_own];
+    acc[0] = s.area[i_own];
+    acc[1] = s.area[n + i_own];
+  }
   __syncthreads();
   for (int64_t k = kl0; k < kl1; ++k) {
     const int cur = (int)(k & 1);
@@ -181,7 +196,24 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
         by += __shfl_xor(by, off, 64);
         bz += __shfl_xor(bz, off, 64);
       }
-      if (i < n && sub == 0) {
+      if (own) {  // (one pass: i == i_own)
+        D4 mo;
+        if constexpr (sizeof(T) == 8) {
+          const P4 ml = mc[i];
+          mo = D4{ml.x, ml.y, ml.z, 0.0};
+        } else {
+          mo = ldg(s.m64 + (int64_t)cur * s.stride + i);
+        }
+        D4 mn;
+        mxsum += np_epilogue<kScan>(s, i, k, cur, (double)bx, (double)by, (double)bz,
+                                    NPState{mo, nn_own}, acc, &mn);
+        P4 v;
+        v.x = mn.x;
+        v.y = mn.y;
+        v.z = mn.z;
+        v.w = 0;
+        mom[(int64_t)(cur ^ 1) * nmax + i] = v;
+      } else if (i < n && sub == 0) {
         const double mx = np_epilogue<kScan>(s, i, k, cur, (double)bx, (double)by, (double)bz);
         mxsum += mx;
         if (s.field_only) continue;
@@ -207,6 +239,25 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
       }
     }
   }
+}
+
+// Latency floor of a resident step: kResThreads threads pass one value each through a
+// double-buffered LDS array across one barrier per step, as a resident step passes the
+// moments to the next step's sums; the last value goes to sink so that nothing is
+// optimised away.
+__global__ __launch_bounds__(kResThreads) void k_empty_steps(int64_t steps, double* sink) {
+  __shared__ double v[2][kResThreads];
+  const int t = threadIdx.x;
+  double a = (double)t;
+  v[0][t] = a;
+  __syncthreads();
+  for (int64_t k = 0; k < steps; ++k) {
+    const int cur = (int)(k & 1);
+    a += v[cur][(t + 1) % kResThreads];
+    v[cur ^ 1][t] = a;
+    __syncthreads();
+  }
+  if (t == 0) sink[0] = a;
 }
 
 // ---------------------------------------------------------------------------
@@ -917,6 +968,11 @@ hipError_t launch_field_plan(const SysDesc& s, SysDesc* d_desc, int4* tiles, int
   const int cnt = max(max(s.n, tiles_per_part * nsplit), max(nublocks, 1));
   hipLaunchKernelGGL(k_field_plan, dim3((cnt + 255) / 256), dim3(256), 0, st, s, d_desc, tiles,
                      tiles_per_part, nsplit, ublocks, nublocks, m_in);
+  return hipGetLastError();
+}
+
+hipError_t launch_empty_steps(int64_t steps, double* sink, hipStream_t st) {
+  hipLaunchKernelGGL(k_empty_steps, dim3(1), dim3(kResThreads), 0, st, steps, sink);
   return hipGetLastError();
 }
 

@@ -211,10 +211,14 @@ __device__ __forceinline__ void np_dhdip(const SysDesc& s, int i, int64_t k, dou
   }
 }
 
-// Outputs of the step: the new moment into buffer cur^1 (and its FP32 copy), the area,
-// the diagnostics; returns the new moment's component along e_H.
+// Outputs of the step: the new moment into buffer cur^1 (and its FP32 copy, and *mnew
+// when given), the area, the diagnostics; returns the new moment's component along e_H.
+// acc, when given, holds the particle's area accumulator (sum, compensation) in the
+// caller's registers: it is read from there instead of memory and kept up to date (the
+// memory copy is written as well).
 __device__ __forceinline__ double np_out(const SysDesc& s, int i, int64_t k, int cur,
-                                         const NPIn& q, const NPResult& r) {
+                                         const NPIn& q, const NPResult& r, double* acc = nullptr,
+                                         D4* mnew = nullptr) {
   const double ex = s.eh[0], ey = s.eh[1], ez = s.eh[2];
   const int nxt = cur ^ 1;
   D4 mn;
@@ -223,6 +227,7 @@ __device__ __forceinline__ double np_out(const SysDesc& s, int i, int64_t k, int
   mn.z = r.mz;
   mn.w = 0.0;
   s.m64[(int64_t)nxt * s.stride + i] = mn;
+  if (mnew) *mnew = mn;
   if (s.m32) {
     F4 mf;
     mf.x = (float)r.mx;
@@ -235,10 +240,14 @@ __device__ __forceinline__ double np_out(const SysDesc& s, int i, int64_t k, int
   if (k >= s.kept0) {
     const D4& mo = q.mo;
     const double mh_old = mo.x * ex + mo.y * ey + mo.z * ez;
-    double sum = s.area[i], comp = s.area[s.n + i];
+    double sum = acc ? acc[0] : s.area[i], comp = acc ? acc[1] : s.area[s.n + i];
     neumaier_add(sum, comp, s.Ms * q.Bext * (mh_new - mh_old));
     s.area[i] = sum;
     s.area[s.n + i] = comp;
+    if (acc) {
+      acc[0] = sum;
+      acc[1] = comp;
+    }
   }
   if (s.diag) {
     double* d = s.diag + (int64_t)i * 8;
@@ -266,11 +275,12 @@ __device__ __forceinline__ NPState np_state(const SysDesc& s, int i, int cur) {
 // Steps iii-vii for particle i of system s with the reduced dipolar sum (ax, ay, az)
 // from the moment and axis st (buffer cur); writes buffer cur^1, accumulates the area,
 // and returns the new moment's component along the field direction e_H. kScan as for
-// np_update.
+// np_update; acc and mnew as for np_out.
 template <bool kScan>
 __device__ __forceinline__ double np_epilogue(const SysDesc& s, int i, int64_t k, int cur,
                                               double ax, double ay, double az,
-                                              const NPState& st) {
+                                              const NPState& st, double* acc = nullptr,
+                                              D4* mnew = nullptr) {
   if (s.field_only) {
     double* d = s.diag + (int64_t)i * 8;
     d[0] = s.Bscale * ax;
@@ -282,7 +292,7 @@ __device__ __forceinline__ double np_epilogue(const SysDesc& s, int i, int64_t k
   const NPIn q = np_in(s, k, ax, ay, az, st.mo, st.nn);
   const NPResult r = np_update<kScan>(s.np, q.Bx, q.By, q.Bz, q.nn.x, q.nn.y, q.nn.z, q.mo.x,
                                       q.mo.y, q.mo.z, s.seed, s.stream, i, k);
-  return np_out(s, i, k, cur, q, r);
+  return np_out(s, i, k, cur, q, r, acc, mnew);
 }
 
 template <bool kScan>

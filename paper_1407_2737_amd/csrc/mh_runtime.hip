@@ -37,6 +37,7 @@ hipError_t launch_field_plan(const SysDesc& s, SysDesc* d_desc, int4* tiles, int
                              int nsplit, int2* ublocks, int nublocks, const double* m_in,
                              hipStream_t st);
 hipError_t launch_field_out(const double* diag, double* B, int n, hipStream_t st);
+hipError_t launch_empty_steps(int64_t steps, double* sink, hipStream_t st);
 int wm_tile_rows();
 int wm_tile_reps();
 int wm_tile_k();
@@ -151,6 +152,7 @@ struct mh_ctx {
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int n_cu = 256;
   DevBuf d_sys;
+  DevBuf d_probe;  // result of the empty-step timing kernel
   PinBuf h_stage;
   std::vector<unsigned char> staged;  // host image of the plan now in d_sys
   std::vector<hipGraphExec_t> timing_graphs;  // graphs of mh_time_kernels, kept to the end
@@ -1305,6 +1307,7 @@ int mh_ctx_destroy(mh_ctx* c) {
   for (hipEvent_t ev : c->tev)
     if (ev) (void)hipEventDestroy(ev);
   c->d_kbase.release();
+  c->d_probe.release();
   c->d_sys.release();
   c->h_stage.release();
   if (c->side) {
@@ -1429,6 +1432,27 @@ int mh_run_batch(mh_asm* const* asms, int32_t count, const int64_t* n_replicas,
 int mh_run_loops(mh_asm* a, int64_t n_replicas, uint64_t seed, void* hip_stream) {
   mh_asm* arr[1] = {a};
   return mh_run_batch(arr, 1, &n_replicas, &seed, hip_stream);
+}
+
+int mh_time_empty_steps(mh_ctx* c, int64_t steps, double* us_per_step) {
+  if (!c || !us_per_step || steps < 1 || steps > 10000000) return MH_EINVAL;
+  if (set_dev(c)) return MH_EDEVICE;
+  int e;
+  if ((e = c->d_probe.ensure(sizeof(double)))) return e;
+  if (!c->tev[0] && (hipEventCreate(&c->tev[0]) != hipSuccess || hipEventCreate(&c->tev[1]) != hipSuccess))
+    return MH_EDEVICE;
+  hipStream_t st = c->stream;
+  float ms = 0.f;
+  // one untimed launch first (code load, clocks), then the timed one
+  if (launch_empty_steps(std::min<int64_t>(steps, 1000), c->d_probe.as<double>(), st) !=
+          hipSuccess ||
+      hipEventRecord(c->tev[0], st) != hipSuccess ||
+      launch_empty_steps(steps, c->d_probe.as<double>(), st) != hipSuccess ||
+      hipEventRecord(c->tev[1], st) != hipSuccess || hipEventSynchronize(c->tev[1]) != hipSuccess ||
+      hipEventElapsedTime(&ms, c->tev[0], c->tev[1]) != hipSuccess)
+    return MH_EDEVICE;
+  *us_per_step = (double)ms * 1e3 / (double)steps;
+  return MH_OK;
 }
 
 int mh_time_kernels(mh_asm* const* asms, int32_t count, int32_t kind, int32_t launches,
