@@ -520,6 +520,7 @@ struct Plan {
   // extremum mode cover them all (wmu[1]: the 200-point scan)
   std::vector<WMGroupItem> wmg, wmu[2];
   int wmg_blocks = 0, wmu_blocks[2] = {0, 0};
+  bool wm_grouped = false;
   std::vector<SysDesc> upd;   // all tiled systems
   std::vector<int2> ublocks;  // (system in upd, block of 256 particles)
   int nmax_res64 = 0, nmax_res32 = 0;
@@ -565,8 +566,16 @@ void add_tiled(Plan& pl, int fp64, int kind, const std::vector<SysDesc>& reps, i
 // Block ranges of the grouped matrix-form launches. Products go longest first (the
 // longest k range, then the most blocks), each range starting at a multiple of 8 so that
 // every block keeps its XCD; updates go largest first. A block's work is the same as
-// in the system's own launch, so the results do not depend on the grouping.
-void group_wm(Plan& pl) {
+// in the system's own launch, so the results do not depend on the grouping. Returns
+// false (no grouping: one launch per system) where a grouped grid would exceed the
+// one-dimensional grid's range.
+bool group_wm(Plan& pl) {
+  int64_t tot_g = 0, tot_u = 0;
+  for (const WMItem& it : pl.wm) {
+    tot_g += ((int64_t)it.g.n_rtiles * it.g.n_ctiles * wm_ksplit() + 7) / 8 * 8;
+    tot_u += (it.a->n + 255) / 256 * it.a->R;
+  }
+  if (tot_g > ((int64_t)1 << 30) || tot_u > ((int64_t)1 << 30)) return false;
   std::vector<int> ord(pl.wm.size());
   for (size_t q = 0; q < ord.size(); ++q) ord[q] = (int)q;
   auto gemm_blocks = [](const WMArgs& g) { return g.n_rtiles * g.n_ctiles * wm_ksplit(); };
@@ -598,6 +607,7 @@ void group_wm(Plan& pl) {
     pl.wmu[sc].push_back(x);
     pl.wmu_blocks[sc] += x.nb;
   }
+  return true;
 }
 
 // Host image of a run's plan: arrays placed at 256-byte aligned offsets of one blob,
@@ -737,7 +747,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
     fin.push_back({a, {first, (int)all.size()}});
     if (a->p.precision == MH_BF16X3_WM) pl.wm.push_back(WMItem{a, first, wm_args(a)});
   }
-  if (pl.wm.size() >= 2) group_wm(pl);
+  if (pl.wm.size() >= 2) pl.wm_grouped = group_wm(pl);
   // descriptors and tile lists, laid out as one blob; a plan identical to the one the
   // context staged last (a server chunk of the same requests) is not uploaded again
   PlanBlob blob;
@@ -778,7 +788,7 @@ int run_systems(std::vector<mh_asm*>& asms, const std::vector<int64_t>& Rs,
   // the matrix-form launches of one step: kind 2 the products, kind 4 the updates
   auto wm_launches = [&](int kind, const int64_t* kb, int64_t koff) -> hipError_t {
     hipError_t r = hipSuccess;
-    if (pl.wm.size() >= 2) {
+    if (pl.wm_grouped) {
       if (kind == 2) return launch_wm_gemm_group(d_wmg, (int)pl.wmg.size(), pl.wmg_blocks, st);
       for (int sc = 0; sc < 2 && r == hipSuccess; ++sc)
         if (!pl.wmu[sc].empty())
