@@ -96,8 +96,16 @@ def cpu_baseline(assemblies, budget_s=15.0, pool_s=10.0):
         t1 = time.perf_counter()
         ks = pool.map(_oracle_replica_steps, [(r, pool_s) for r in range(procs)])
         dt_pool = time.perf_counter() - t1
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         None)
+    except OSError:
+        pass
     return {"value": a.n * k / dt, "unit": "NP·steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} steps of the 20 mT assembly (N={a.n}), single-threaded numpy FP64",
+            "host": {"cpu_model": model, "os_cpu_count": os.cpu_count()},
             "pool": {"value": a.n * sum(ks) / dt_pool, "cores": procs,
                      "sample": f"{procs} processes, one replica each (own Philox stream), "
                                f"{sum(ks)} steps in all of the same assembly, one thread each"}}
