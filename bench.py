@@ -668,12 +668,15 @@ def bench_served(args, mh, W):
 
     all_engines = {"plain_fp32": mh.FP32_FIELD, "matrix_bf16x3": mh.BF16X3_WM}
     engines = {k: v for k, v in all_engines.items() if k.split("_")[0] in args.engines.split(",")}
-    out = {}
+    out = {name: {} for name in engines}
     for name, prec in engines.items():
-        sat = serve(prec, geo[:n_sat], [0.0] * n_sat, f"{name} saturation")
-        out[name] = {"saturated": dict(sat, req_per_s=n_sat / sat["seconds"])}
+        if n_sat > 0:  # --sat-requests 0: rate phases only, at the given --lambda0
+            sat = serve(prec, geo[:n_sat], [0.0] * n_sat, f"{name} saturation")
+            out[name]["saturated"] = dict(sat, req_per_s=n_sat / sat["seconds"])
     # arrival rates are factors of the plain engine's saturated rate (measured here, or
     # given when the engines run in separate processes)
+    if not args.lambda0 and "saturated" not in out.get("plain_fp32", {}):
+        raise SystemExit("served: give --lambda0 when the plain engine's saturation is not run")
     lam0 = args.lambda0 or out["plain_fp32"]["saturated"]["req_per_s"]
     rng = np.random.default_rng(77)
     for k, fct in enumerate(rates):
@@ -684,7 +687,7 @@ def bench_served(args, mh, W):
             out[name][f"rate_{fct:g}x"] = dict(serve(prec, items, gaps, f"{name} {fct:g}x"),
                                                arrival_req_per_s=fct * lam0)
     eng = out.get("matrix_bf16x3") or out["plain_fp32"]
-    main = eng.get("rate_0.7x") or eng["saturated"]
+    main = eng.get("rate_0.7x") or eng.get("saturated") or next(iter(eng.values()))
     return {"metric": "served loops/s; p50/p99 request latency at SAR err<=1%",
             "value": main["loops_per_s"], "unit": "loops/s", "n_gpus": 1,
             "steps": n_rate * len(rates), "warmup": n_sat,
