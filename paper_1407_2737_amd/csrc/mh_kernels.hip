@@ -85,8 +85,7 @@ __device__ __forceinline__ void dip_pair(T xi, T yi, T zi, const P4& pj, const M
 // Fixed-order block sum of one double per thread (blockDim.x == 256).
 __device__ __forceinline__ double block_sum_256(double v, double* red) {
   const int tid = threadIdx.x;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum(v);
   if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
   const double t = (red[0] + red[1]) + (red[2] + red[3]);
@@ -109,8 +108,7 @@ static_assert(kResThreads / 64 == kRecSlots, "one loop-record slot per resident 
 // pairwise tree over the waves.
 __device__ __forceinline__ double block_sum_res(double v, double* red) {
   const int tid = threadIdx.x;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = wave_sum(v);
   if ((tid & 63) == 0) red[tid >> 6] = v;
   __syncthreads();
   double w[kResThreads / 64];
@@ -230,8 +228,7 @@ __global__ __launch_bounds__(kResThreads) void k_resident(const SysDesc* __restr
     if (k >= s.kept0 && !s.field_only) {
       if (s.rec_slots == kRecSlots) {  // one slot per wave: no block reduction, no barrier
         double v = mxsum;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        v = wave_sum(v);
         if ((tid & 63) == 0) s.recpart[(k - s.kept0) * kRecSlots + (tid >> 6)] = v;
       } else {
         const double tot = block_sum_res(mxsum, red);
@@ -481,8 +478,7 @@ __global__ __launch_bounds__(256) void k_update(const SysDesc* __restrict__ syst
   }
   if (k >= s.kept0 && !s.field_only) {  // the loop record: wave sums or their total
     double v = mx;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_sum(v);
     double* rp = s.recpart + ((k - s.kept0) * s.ntiles + bl.y) * s.rec_slots;
     if (s.rec_slots == kRecSlots) {
       if ((threadIdx.x & 63) == 0) rp[threadIdx.x >> 6] = v;
@@ -590,8 +586,7 @@ __global__ __launch_bounds__(192) void k_update3(const SysDesc* __restrict__ sys
   }
   if (role == 0 && k >= s.kept0 && !s.field_only) {  // uniform over the wave
     double v = mx;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_sum(v);
     if (t == 0) s.recpart[((k - s.kept0) * s.ntiles + bl.y) * kRecSlots + part] = v;
     // (rec_slots == kRecSlots here: the launch holds at most kUpdate3MaxBlocks blocks)
   }

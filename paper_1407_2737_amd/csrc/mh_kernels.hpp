@@ -118,6 +118,31 @@ __host__ __device__ inline double applied_field(const SysDesc& s, int64_t k) {
   return s.Bmax * cos(2.0 * kPi * (double)k / (double)s.S);
 }
 
+// v of the lane N places along in the lane's row of 16 (DPP row rotation).
+template <int N>
+__device__ __forceinline__ double dpp_row_ror(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x120 + N, 0xF, 0xF, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over a wave's 64 lanes (all active), every lane getting the total, in a fixed
+// tree: lane l adds lane l ^ 32, then l ^ 16, ..., l ^ 1. The last four steps are DPP
+// rotations within rows of 16, which fetch lane l ^ 8, ^ 4, ^ 2, ^ 1 once the values
+// repeat with period 16, 8, 4 and 2 along the row (as they do after the steps before),
+// at register latency instead of an LDS permute's.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += __shfl_xor(v, 32, 64);
+  v += __shfl_xor(v, 16, 64);
+  v += dpp_row_ror<8>(v);
+  v += dpp_row_ror<4>(v);
+  v += dpp_row_ror<2>(v);
+  v += dpp_row_ror<1>(v);
+  return v;
+}
+
 // Loads through the global address space as one vector. The pointers come from
 // descriptors in memory, where the compiler cannot infer the address space and would
 // emit flat loads, whose waits also wait on LDS and scalar loads.

@@ -357,8 +357,7 @@ __device__ __forceinline__ void wm_update_block(const SysDesc* __restrict__ syst
   }
   if (k >= s.kept0 && !s.field_only) {
     double v = mx;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_sum(v);
     double* rp = s.recpart + ((k - s.kept0) * s.ntiles + bx) * s.rec_slots;
     if (s.rec_slots == kRecSlots) {
       if ((threadIdx.x & 63) == 0) rp[threadIdx.x >> 6] = v;
