@@ -890,8 +890,12 @@ hipError_t set_resident_lds_limit() {
   const void* fns[] = {(const void*)k_resident<double, false>, (const void*)k_resident<float, false>,
                        (const void*)k_resident<double, true>, (const void*)k_resident<float, true>};
   for (const void* f : fns) {
-    const hipError_t e =
-        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64);
+    // the whole 160 KB of a CU's LDS less the kernel's static arrays
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, f);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024 - (int)attr.sharedSizeBytes);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
