@@ -49,3 +49,11 @@ def test_config_samplers():
     reqs = W.request_stream(count=200)
     assert all(100 <= q["n"] <= 8000 and 3 <= q["P"] <= 10 for q in reqs)
     assert all(np.diff([q["t"] for q in reqs]) > 0)
+
+
+def test_request_stream_prefix_does_not_depend_on_count():
+    """The served bench takes its phases as slices of one stream: the first k requests
+    (parameters and arrival times) are the same whatever the stream's length."""
+    short, long = W.request_stream(count=18), W.request_stream(count=40)
+    for a, b in zip(short, long):
+        assert a == b
